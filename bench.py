@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the LBM time step on one MI355X.
+
+Default workload: D3Q19, 256^3 fully periodic, FP64, 3D Taylor-Green vortex
+(U0 = 0.05) plus U(-1e-6, 1e-6) population noise (seed 2), tau = 0.6.  A
+timed step is one lbm_step(1) -- pull-stream, bounce-back, moments,
+equilibrium, IMEX-BGK relaxation, forcing and store fused in one kernel --
+and the timed region ends with one Monitor reduction (lbm_reduce), as the
+paper's main loop monitors every interv steps.
+
+Prints one JSON line: MLUPS (lattice points x steps / time / 1e6, counting
+every node of the domain), the HBM roofline of the dominant kernel from
+algorithmic bytes per lattice update (2 Q sizeof(storage)) and its average
+launch duration measured with HIP events on the launch stream, and the CPU
+oracle's MLUPS on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+METRIC = "MLUPS & % of HBM peak, D3Q19 256³ FP64 vs FP16-store; adjoint/forward ratio"
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+DTYPE_NAME = {"f64": "f64", "f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32"}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=256, help="cube edge of the workload")
+    ap.add_argument("--storage", default="f64", choices=sorted(STORAGE_BYTES))
+    ap.add_argument("--pattern", default="ab", choices=["ab", "aa"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP16-storage comparison line")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of the population buffer size "
+                         "(reference point for HBM byte counters)")
+    return ap.parse_args()
+
+
+def run_gpu(n, storage, pattern, steps, warmup, copy_probe=False):
+    import numpy as np
+    import torch
+
+    from paper_2201_11330_amd import lbm
+    from paper_2201_11330_amd import workloads as W
+
+    dims = (n, n, n)
+    rho, u = W.taylor_green_3d(n, U0=0.05)
+    noise = W.population_noise(W.D3Q19, dims, 1e-6, seed=2)
+    torch.cuda.set_device(0)
+    sim = lbm.LBM(lbm.D3Q19, n, n, n, 0.6, storage=storage, aa=(pattern == "aa"))
+    sim.init_equilibrium(rho, u, noise)
+    del noise
+    stream = sim.stream
+    red0 = sim.reduce()
+    for _ in range(warmup):
+        sim.step(1)
+    torch.cuda.synchronize()
+
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        events[0].record(stream)
+        for i in range(steps):
+            sim.step(1)
+            events[i + 1].record(stream)
+        red = sim.reduce()  # Monitor: synchronises the stream
+        t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    per_launch = [events[i].elapsed_time(events[i + 1]) for i in range(steps)]
+    total_ms = events[0].elapsed_time(t_end)
+    result = {
+        "dims": dims,
+        "storage": storage,
+        "pattern": pattern,
+        "total_ms": total_ms,
+        "wall_s": wall,
+        "launch_ms_mean": float(np.mean(per_launch)),
+        "launch_ms_median": float(np.median(per_launch)),
+        "mass_drift": abs(red["mass"] - red0["mass"]) / red0["mass"],
+        "ke_ratio": red["ke"] / red0["ke"],
+        "unstable": red["unstable"],
+    }
+    sim.close()
+    if copy_probe:
+        nbytes = 19 * n ** 3 * STORAGE_BYTES[storage]
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 20
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        result["copy_probe"] = {"bytes": nbytes, "ms": ms, "gbs": 2 * nbytes / ms / 1e6}
+    return result
+
+
+def cpu_baseline(n, target_s):
+    """The oracle, as it stands, on the host cores: whole-domain steps of the
+    same workload, as many as fit in about target_s seconds."""
+    import numpy as np
+
+    import oracle
+    from paper_2201_11330_amd import workloads as W
+
+    dims = (n, n, n)
+    rho, u = W.taylor_green_3d(n, U0=0.05)
+    noise = W.population_noise(W.D3Q19, dims, 1e-6, seed=2)
+    s = oracle.Sim(oracle.D3Q19, n, n, n, tau=0.6)
+    s.init_equilibrium(rho, u, noise)
+    del noise
+    t0 = time.perf_counter()
+    s.step(1)
+    t1 = time.perf_counter() - t0
+    k = int(max(1, min(50, math.floor(target_s / max(t1, 1e-9)))))
+    t0 = time.perf_counter()
+    s.step(k)
+    dt = time.perf_counter() - t0
+    s.close()
+    mlups = n ** 3 * k / dt / 1e6
+    return {
+        "value": round(mlups, 3),
+        "unit": "MLUPS",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"D3Q19 {n}^3 FP64 Taylor-Green, {k} whole-domain steps after 1 untimed "
+                  f"({dt:.1f} s), AoS paper-order oracle, OpenMP",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not built)"}))
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    n = args.n
+    r = run_gpu(n, args.storage, args.pattern, args.steps, args.warmup, args.copy_probe)
+    nodes = n ** 3
+    mlups = nodes * args.steps / (r["total_ms"] * 1e-3) / 1e6
+    blu = 2 * 19 * STORAGE_BYTES[args.storage]
+    achieved = blu * nodes / (r["launch_ms_mean"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["total_ms"] / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE_NAME[args.storage],
+        "data": "synthetic",
+        "config": {
+            "workload": f"D3Q19 {n}^3 periodic 3D Taylor-Green U0=0.05 + 1e-6 noise, tau=0.6, "
+                        f"{args.storage} storage, {args.pattern.upper()} fused pull kernel",
+            "lattice": "D3Q19", "nx": n, "ny": n, "nz": n, "tau": 0.6,
+            "storage": args.storage, "pattern": args.pattern,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": f"k_step_{args.pattern}<D3Q19,{args.storage}>",
+            "bytes_per_update": blu,
+            "launch_ms_mean": round(r["launch_ms_mean"], 5),
+            "launch_ms_median": round(r["launch_ms_median"], 5),
+        },
+        "checks": {"mass_drift": r["mass_drift"], "ke_ratio": r["ke_ratio"],
+                   "unstable": r["unstable"]},
+    }
+    if "copy_probe" in r:
+        out["copy_probe"] = r["copy_probe"]
+    if not args.no_extras and args.storage == "f64":
+        r16 = run_gpu(n, "f16", args.pattern, args.steps, args.warmup)
+        m16 = nodes * args.steps / (r16["total_ms"] * 1e-3) / 1e6
+        a16 = 2 * 19 * 2 * nodes / (r16["launch_ms_mean"] * 1e-3) / 1e9
+        out["fp16_store"] = {"mlups": round(m16, 1), "speedup_vs_f64": round(m16 / mlups, 3),
+                             "achieved_gbs": round(a16, 1),
+                             "frac": round(a16 / HBM_PEAK_GBS, 4)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * lbm.h -- C interface of liblbm.so, the gfx950 (MI355X) implementation of
+ * the lattice Boltzmann time step of IMEXLBM (Liu, Patel, Balakrishnan, Lee,
+ * "IMEXLBM 1.0: A Proxy Application based on the Lattice Boltzmann Method
+ * for solving CFD problems on GPUs", 2022).
+ *
+ * The calls follow the paper's program structure (Sec. 3.1):
+ *   lbm_create           DataInput + InitLattice + SetGeometry (Sec. 3.1, Table 4)
+ *   lbm_bind             AllocateArrays / TARGET ENTER DATA: the caller's device
+ *                        buffers and stream become the state of the context
+ *   lbm_init_equilibrium InitUP + InitPDF: f = feq(rho, u) (Sec. 2.2)
+ *   lbm_step             n passes of Collision -> BoundaryCondition ->
+ *                        Propagation -> PostProcessing (Sec. 3.1; Eqs.
+ *                        (collision), (bb), (propagation))
+ *   lbm_moments          PostProcessing outputs p/c_s^2 and u (Sec. 2.1)
+ *   lbm_reduce           Monitor (Sec. 3.6): global reductions
+ *   lbm_destroy          DeAllocateArrays / TARGET EXIT DATA
+ *
+ * Conventions shared by every call:
+ *   - A "field" is a device array in the canonical structure-of-arrays order
+ *     [component][z][y][x], x fastest, N = nx*ny*nz nodes per component:
+ *     rho is [N], u is [3][N] (u_z = 0 for D2Q9), populations are [Q][N].
+ *   - tau is the lattice relaxation time: omega = 1/tau, nu = (tau - 1/2)/3.
+ *     The paper's tau (Eq. (collision), relaxation parameter
+ *     1/(tau/dt + 1/2), dt = 1) is this tau minus 1/2.
+ *   - "rho" is p/c_s^2 = sum_a f_a, the quantity the Collision listing uses
+ *     as 3p (Sec. 3.6); c_s^2 = 1/3 and rho0 = 1 (Table 3).
+ *   - The velocity is u = (sum_a e_a f_a + F/2)/rho0: the incompressible
+ *     model's moment (Sec. 2.1) shifted by half the body force F, which
+ *     enters the collision as t_a [3 (e_a - u).F + 9 (e_a.u)(e_a.F)] times
+ *     (1 - omega/2) (trapezoidal forcing; the paper gives no force term).
+ *   - Walls are halfway bounce-back (Eq. (bb)): a population whose pull
+ *     source x - e_a is solid is replaced by the opposite population of the
+ *     same node.  Solid nodes carry no state.
+ *   - The caller owns every device buffer and the stream (e.g. torch tensors
+ *     and torch's current stream); they must outlive their use by the
+ *     context.  The library owns the context and a small device scratch for
+ *     reductions, allocated in lbm_bind and freed in lbm_destroy.
+ *   - Every call returns LBM_OK (0) or a negative lbm_status and never
+ *     throws.  Arguments are checked on the host before any launch.  A HIP
+ *     failure returns LBM_EHIP; lbm_last_error() then holds the HIP error
+ *     text.  Kernel faults are asynchronous and surface at the next call
+ *     that synchronises.  A context is not thread-safe; separate contexts
+ *     are independent.
+ */
+#ifndef IMEXLBM_LBM_H
+#define IMEXLBM_LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* bad argument; nothing was launched */
+    LBM_ENOTBOUND = -2, /* call needs lbm_bind first */
+    LBM_EHIP = -3,      /* HIP runtime error (text in lbm_last_error) */
+    LBM_EUNSTABLE = -4, /* lbm_reduce found a non-finite population */
+    LBM_ESTATE = -5     /* call not valid in the context's current state */
+} lbm_status;
+
+/* Discrete velocity models of Sec. 2.1.  D2Q9 is numbered as printed there
+ * (lexicographic in (e_x, e_y), e_x slowest); D3Q19 extends that rule to
+ * three dimensions without the 8 corners.  In both the opposite of a is
+ * Q - 1 - a. */
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 } lbm_lattice;
+
+/* Storage of the populations in device memory.  LBM_F64 stores f and
+ * computes in FP64 (the paper's precision).  The others store the deviation
+ * f_a - t_a and compute in FP32: LBM_F32 in FP32, LBM_F16_DEV in IEEE half,
+ * LBM_BF16_DEV in bfloat16, each rounded to nearest-even on store.
+ * Reductions accumulate in FP64 for every storage. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_DEV = 2, LBM_BF16_DEV = 3 } lbm_storage;
+
+/* Boundary of one axis. */
+typedef enum {
+    LBM_PERIODIC = 0,      /* wrap-around, done inside the kernels */
+    LBM_SOLID_ENDS = 1,    /* first and last planes are solid nodes; walls
+                              lie half a cell inside them */
+    LBM_WALLS_OUTSIDE = 2  /* every plane is fluid; walls lie half a cell
+                              outside the first and last planes */
+} lbm_axis_bc;
+
+typedef struct {
+    int axis[3]; /* lbm_axis_bc for x, y, z */
+} lbm_bc;
+
+/* lbm_create flags. */
+enum {
+    LBM_FLAG_AA = 1 /* in-place AA pattern: one population buffer instead of two */
+};
+
+/*
+ * Creates a context for an nx*ny*nz box.  Checks (LBM_EINVAL otherwise):
+ * tau > 1/2 (tau = +inf is pure streaming, allowed only with F = 0);
+ * every dimension >= 1 and >= 3 on an LBM_SOLID_ENDS axis; D2Q9 needs
+ * nz = 1, a periodic z axis and F_z = 0; F finite; N = nx*ny*nz < 2^31;
+ * flags only LBM_FLAG_AA.  force may be NULL (no force); bc may be NULL
+ * (fully periodic).  No device work happens here.
+ */
+lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz, double tau,
+                      const double force[3], const lbm_bc* bc, lbm_storage storage,
+                      unsigned flags);
+
+/* Bytes of one population buffer: Q * N * sizeof(storage element). */
+size_t lbm_buffer_bytes(const lbm_ctx* ctx);
+
+/*
+ * Binds device memory and a stream.  buf_a and buf_b are two population
+ * buffers of lbm_buffer_bytes() each (buf_b must be NULL with LBM_FLAG_AA
+ * and non-NULL otherwise), 256-byte aligned, on the current device.
+ * hip_stream is a hipStream_t (NULL = the null stream); every later launch
+ * goes to it, in order.  Allocates the reduction scratch.  The state is
+ * undefined until lbm_init_equilibrium or lbm_set_populations.
+ */
+lbm_status lbm_bind(lbm_ctx* ctx, void* buf_a, void* buf_b, void* hip_stream);
+
+/*
+ * InitPDF: f_a = t_a [rho + rho0 (3 e_a.u + 4.5 (e_a.u)^2 - 1.5 u.u)]
+ * (Eq. (incompressible_feq)) on every fluid node, plus noise_a if noise is
+ * not NULL.  rho [N], u [3][N], noise [Q][N]: device FP64 fields.
+ * Asynchronous on the bound stream.
+ */
+lbm_status lbm_init_equilibrium(lbm_ctx* ctx, const double* rho, const double* u,
+                                const double* noise);
+
+/*
+ * Sets / reads the populations f^n of the paper's f array after the last
+ * Propagation (device FP64 field [Q][N]; solid nodes are ignored on set and
+ * read back as 0).  For the FP64 storage the round trip is bit-exact; the
+ * other storages round f - t_a on set.  Asynchronous on the bound stream.
+ */
+lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f);
+lbm_status lbm_get_populations(lbm_ctx* ctx, double* f);
+
+/* Advances n >= 0 time steps.  Asynchronous on the bound stream. */
+lbm_status lbm_step(lbm_ctx* ctx, int n);
+
+/*
+ * PostProcessing of the current f^n: rho = sum_a f_a [N] and
+ * u = (sum_a e_a f_a + F/2)/rho0 [3][N], written as FP64 (out_is_f32 = 0) or
+ * FP32 (out_is_f32 = 1) device fields; either pointer may be NULL.  Solid
+ * nodes read 0.  Asynchronous on the bound stream.
+ */
+lbm_status lbm_moments(lbm_ctx* ctx, void* rho, void* u, int out_is_f32);
+
+/*
+ * Monitor: total mass sum rho, kinetic energy (rho0/2) sum |u|^2 and
+ * max |u| over the fluid nodes, accumulated in FP64 in a fixed order (the
+ * result does not depend on scheduling).  Host outputs, any may be NULL.
+ * Synchronises the bound stream.  Returns LBM_EUNSTABLE (outputs still
+ * written) when a population is NaN or infinite.
+ */
+lbm_status lbm_reduce(lbm_ctx* ctx, double* mass, double* kinetic_energy, double* umax);
+
+/* Time steps taken since the last init/set (the AA parity is its low bit). */
+long long lbm_steps_taken(const lbm_ctx* ctx);
+
+/* Frees the context and its scratch (not the caller's buffers).  NULL is a
+ * no-op. */
+lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* Static text for a status code. */
+const char* lbm_status_string(lbm_status status);
+/* Detail of the last error raised on this thread (never NULL). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -53,8 +53,15 @@ def _load():
     lib.orc_adjoint.argtypes = (
         [ctypes.c_int] * 4 + [ctypes.c_double, _dp, _ip, _dp, _dp, _dp, ctypes.c_int, _dp, _dp,
                               _dp, _dp])
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def num_threads():
+    """OpenMP threads the oracle's loops run on."""
+    return _load().orc_num_threads()
 
 
 def _d(a):

@@ -22,6 +22,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -370,6 +371,9 @@ int orc_reduce(const orc_sim* s, double* mass, double* ke, double* umax, long* n
     if (nonfinite) *nonfinite = bad;
     return 0;
 }
+
+/* Threads the oracle's parallel loops use (reported with its timings). */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Node-level entry points for the pins.                                     */

@@ -33,6 +33,8 @@ int orc_moments(const orc_sim* s, double* rho, double* u);
 int orc_geometry(const orc_sim* s, unsigned char* geo);
 int orc_reduce(const orc_sim* s, double* mass, double* ke, double* umax, long* nonfinite);
 
+int orc_num_threads(void);
+
 int orc_lattice_tables(int lattice, int* Q, int* D, int* e, double* t);
 int orc_equilibrium_node(int lattice, double rho, const double u[3], double* feq);
 int orc_collide_node(int lattice, double tau, const double F[3], const double* f, double* fb);

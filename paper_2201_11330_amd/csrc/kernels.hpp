@@ -1,0 +1,595 @@
+// Device code of the LBM time step for gfx950.
+//
+// Layout: one population buffer is structure-of-arrays, Q planes of N
+// nodes, plane a at element offset a*N, node (x, y, z) at in-plane index
+// x + nx*(y + ny*z) (x fastest).  One work-item owns one node; 256-item
+// workgroups cover a (BX x BY) tile of an x-y plane with BX a power of two
+// (the full row when nx <= 256), so the 64 lanes of a wavefront touch 64
+// consecutive nodes of a row and every plane access is coalesced.
+//
+// Two-lattice scheme (AB): the stored state is the post-collision
+// population f* of the previous step.  One launch pulls
+// f_a(x) = f*_a(x - e_a) (Eq. (propagation)), or f*_abar(x) when x - e_a is
+// a wall (Eq. (bb)), takes the moments, collides (Eq. (collision)) and
+// writes f*(x) to the other buffer: 2*Q*sizeof(storage) bytes per node.
+//
+// AA pattern (one buffer): even steps read and write the node's own slots,
+// writing f*_a to slot abar; odd steps read the neighbours' opposite slots
+// and write back to where the next even step finds them.  A work-item
+// reads and writes the same set of addresses, so the update is in place.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "lattice.hpp"
+
+namespace imexlbm {
+
+enum AxisBC : int { kPeriodic = 0, kSolidEnds = 1, kWallsOutside = 2 };
+
+// How a stored state maps to the paper's post-propagation f^n.
+enum GatherMode : int {
+    kPull = 0,      // AB state, and AA before an odd step with slots flipped
+    kPullFlip = 1,  // AA before an odd step: f^n_a(x) = A[abar](x - e_a)
+    kLocal = 2      // AA before an even step: f^n_a(x) = A[a](x)
+};
+
+// ---------------------------------------------------------------------------
+// Storage traits: element type in memory, arithmetic type, conversions.
+
+template <class S>
+struct Store;
+
+template <>
+struct Store<double> {
+    using C = double;
+    static constexpr bool kDeviation = false;
+    __device__ static C load(double v) { return v; }
+    __device__ static double save(C v) { return v; }
+};
+
+template <>
+struct Store<float> {
+    using C = float;
+    static constexpr bool kDeviation = true;
+    __device__ static C load(float v) { return v; }
+    __device__ static float save(C v) { return v; }
+};
+
+template <>
+struct Store<__half> {
+    using C = float;
+    static constexpr bool kDeviation = true;
+    __device__ static C load(__half v) { return __half2float(v); }
+    __device__ static __half save(C v) { return __float2half_rn(v); }
+};
+
+template <>
+struct Store<__hip_bfloat16> {
+    using C = float;
+    static constexpr bool kDeviation = true;
+    __device__ static C load(__hip_bfloat16 v) { return __bfloat162float(v); }
+    __device__ static __hip_bfloat16 save(C v) { return __float2bfloat16(v); }  // nearest-even
+};
+
+// ---------------------------------------------------------------------------
+// Compile-time helpers.
+
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+
+// Calls f(std::integral_constant<int, a>) for a = 0..N-1.
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// e * v for a lattice component e in {-1, 0, 1}; the zero term is -0.0, the
+// additive identity the compiler may drop.
+template <int E, class T>
+__device__ __forceinline__ T eterm(T v)
+{
+    if constexpr (E == 1) return v;
+    else if constexpr (E == -1) return -v;
+    else return T(-0.0);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry.
+
+struct Dims {
+    int nx, ny, nz;
+    int bc[3];
+    unsigned N;  // nx*ny*nz
+};
+
+// Coordinates c-1, c, c+1 of one axis (index = shift + 1), wrapped on a
+// periodic axis, and whether each is a wall (a solid plane, or outside the
+// box).  A wall entry keeps coordinate c so its index stays in range.
+struct Axis3 {
+    int c[3];
+    bool wall[3];
+};
+
+template <bool WALLS>
+__device__ __forceinline__ Axis3 axis3(int c, int n, int bc)
+{
+    Axis3 r;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        int s = c + k - 1;
+        bool wall = false;
+        if (!WALLS || bc == kPeriodic) {
+            s = s < 0 ? s + n : (s >= n ? s - n : s);
+        } else if (bc == kSolidEnds) {
+            wall = s <= 0 || s >= n - 1;
+            if (wall) s = c;
+        } else {
+            wall = s < 0 || s >= n;
+            if (wall) s = c;
+        }
+        r.c[k] = s;
+        r.wall[k] = wall;
+    }
+    return r;
+}
+
+__device__ __forceinline__ bool is_solid(const Dims& g, int x, int y, int z)
+{
+    return (g.bc[0] == kSolidEnds && (x == 0 || x == g.nx - 1)) ||
+           (g.bc[1] == kSolidEnds && (y == 0 || y == g.ny - 1)) ||
+           (g.bc[2] == kSolidEnds && (z == 0 || z == g.nz - 1));
+}
+
+// Node of this work-item for the (BX = 1 << bx_shift) x (256 / BX) tiling.
+__device__ __forceinline__ bool node_of_item(const Dims& g, int bx_shift, int& x, int& y, int& z)
+{
+    const int tx = threadIdx.x & ((1 << bx_shift) - 1);
+    const int ty = threadIdx.x >> bx_shift;
+    x = (blockIdx.x << bx_shift) + tx;
+    y = blockIdx.y * (blockDim.x >> bx_shift) + ty;
+    z = blockIdx.z;
+    return x < g.nx && y < g.ny;
+}
+
+// In-plane index of x + sgn*e_a for every a, and whether that node is a wall.
+template <int D, bool WALLS, int SGN>
+__device__ __forceinline__ void link_nodes(const Dims& g, int x, int y, int z,
+                                           unsigned (&idx)[Lattice<D>::Q],
+                                           bool (&wall)[Lattice<D>::Q])
+{
+    const Axis3 ax = axis3<WALLS>(x, g.nx, g.bc[0]);
+    const Axis3 ay = axis3<WALLS>(y, g.ny, g.bc[1]);
+    Axis3 az;
+    if constexpr (D == 3) {
+        az = axis3<WALLS>(z, g.nz, g.bc[2]);
+    } else {
+        az = Axis3{{z, z, z}, {false, false, false}};
+    }
+    static_for<Lattice<D>::Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr int kx = 1 + SGN * kLattice<D>.e[a][0];
+        constexpr int ky = 1 + SGN * kLattice<D>.e[a][1];
+        constexpr int kz = 1 + SGN * kLattice<D>.e[a][2];
+        idx[a] = unsigned(ax.c[kx]) + unsigned(g.nx) * (unsigned(ay.c[ky]) + unsigned(g.ny) * unsigned(az.c[kz]));
+        wall[a] = WALLS && (ax.wall[kx] || ay.wall[ky] || az.wall[kz]);
+    });
+}
+
+// Element offset of the slot holding f^n_a(x) in a stored state (GatherMode),
+// given the pull sources of the node.  The same offsets, written instead of
+// read, import a state: the map is a bijection between (node, direction)
+// pairs of fluid nodes and slots.
+template <int D>
+__device__ __forceinline__ size_t gather_offset(int mode, int a, unsigned own, unsigned src,
+                                                bool wall, unsigned N)
+{
+    const int abar = Lattice<D>::opp(a);
+    if (mode == kLocal) return size_t(a) * N + own;
+    if (mode == kPull) return wall ? size_t(abar) * N + own : size_t(a) * N + src;
+    return wall ? size_t(a) * N + own : size_t(abar) * N + src;  // kPullFlip
+}
+
+// ---------------------------------------------------------------------------
+// Collision at one node (Eq. (collision) with the incompressible equilibrium
+// of Eq. (incompressible_feq), c_s^2 = 1/3, rho0 = 1):
+//   rho = sum f,  u = sum e f + F/2,
+//   feq_a = w_a (rho + 3 e_a.u + 4.5 (e_a.u)^2 - 1.5 u.u),
+//   f*_a = f_a + omega (feq_a - f_a) + (1 - omega/2) w_a (3 (e_a - u).F + 9 (e_a.u)(e_a.F)).
+// The update is affine in f with sum w e = 0, so it maps deviations f - w to
+// deviations unchanged; the reduced-precision storages run it on f - w.
+
+template <class C>
+struct CollideArgs {
+    C omega;
+    C F[3];
+    C k3, k9;  // 3 (1 - omega/2), 9 (1 - omega/2)
+};
+
+template <int D, class C>
+struct Moments {
+    C rho, ux, uy, uz;
+};
+
+template <int D, class C, bool FORCE>
+__device__ __forceinline__ Moments<D, C> node_moments(const C (&f)[Lattice<D>::Q], const C F[3])
+{
+    C rho = C(-0.0), jx = C(-0.0), jy = C(-0.0), jz = C(-0.0);
+    static_for<Lattice<D>::Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        rho += f[a];
+        jx += eterm<kLattice<D>.e[a][0]>(f[a]);
+        jy += eterm<kLattice<D>.e[a][1]>(f[a]);
+        if constexpr (D == 3) jz += eterm<kLattice<D>.e[a][2]>(f[a]);
+    });
+    Moments<D, C> m;
+    m.rho = rho;
+    if constexpr (FORCE) {
+        m.ux = jx + C(0.5) * F[0];
+        m.uy = jy + C(0.5) * F[1];
+        m.uz = D == 3 ? jz + C(0.5) * F[2] : C(0);
+    } else {
+        m.ux = jx;
+        m.uy = jy;
+        m.uz = D == 3 ? jz : C(0);
+    }
+    return m;
+}
+
+template <int D, class C, bool FORCE>
+__device__ __forceinline__ void collide(C (&f)[Lattice<D>::Q], const CollideArgs<C>& p)
+{
+    const Moments<D, C> m = node_moments<D, C, FORCE>(f, p.F);
+    const C usq = m.ux * m.ux + m.uy * m.uy + (D == 3 ? m.uz * m.uz : C(0));
+    const C base = m.rho - C(1.5) * usq;
+    C uF = C(0);
+    if constexpr (FORCE) uF = m.ux * p.F[0] + m.uy * p.F[1] + (D == 3 ? m.uz * p.F[2] : C(0));
+    static_for<Lattice<D>::Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr int ex = kLattice<D>.e[a][0], ey = kLattice<D>.e[a][1], ez = kLattice<D>.e[a][2];
+        const C w = C(kLattice<D>.w[a]);
+        const C edu = eterm<ex>(m.ux) + eterm<ey>(m.uy) + eterm<ez>(m.uz);
+        const C feq = w * (base + edu * (C(3) + C(4.5) * edu));
+        C fs = f[a] + p.omega * (feq - f[a]);
+        if constexpr (FORCE) {
+            const C eF = eterm<ex>(p.F[0]) + eterm<ey>(p.F[1]) + eterm<ez>(p.F[2]);
+            fs += w * (p.k3 * (eF - uF) + p.k9 * edu * eF);
+        }
+        f[a] = fs;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Time-step kernels.
+
+template <class C>
+struct StepArgs {
+    Dims g;
+    int bx_shift;
+    CollideArgs<C> c;
+};
+
+// Fused pull-stream + bounce-back + collide (AB).
+template <int D, class S, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* __restrict__ dst,
+                                                 StepArgs<typename Store<S>::C> p)
+{
+    using C = typename Store<S>::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x, y, z;
+    if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
+    if (WALLS && is_solid(p.g, x, y, z)) return;
+    const unsigned N = p.g.N;
+    const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
+    unsigned idx[Q];
+    bool wall[Q];
+    link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
+    C f[Q];
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr int abar = Lattice<D>::opp(a);
+        const S v = (WALLS && wall[a]) ? src[size_t(abar) * N + own] : src[size_t(a) * N + idx[a]];
+        f[a] = Store<S>::load(v);
+    });
+    collide<D, C, FORCE>(f, p.c);
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        dst[size_t(a) * N + own] = Store<S>::save(f[a]);
+    });
+}
+
+// AA even step: own slots in, opposite own slots out.
+template <int D, class S, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(256) void k_step_aa_even(S* __restrict__ A,
+                                                      StepArgs<typename Store<S>::C> p)
+{
+    using C = typename Store<S>::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x, y, z;
+    if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
+    if (WALLS && is_solid(p.g, x, y, z)) return;
+    const unsigned N = p.g.N;
+    const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
+    C f[Q];
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        f[a] = Store<S>::load(A[size_t(a) * N + own]);
+    });
+    collide<D, C, FORCE>(f, p.c);
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        A[size_t(Lattice<D>::opp(a)) * N + own] = Store<S>::save(f[a]);
+    });
+}
+
+// AA odd step: f_a(x) from slot abar of x - e_a (or slot a of x at a wall);
+// f*_a(x) goes to slot a of x + e_a (or slot abar of x at a wall), which is
+// the address read for direction abar.
+template <int D, class S, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(256) void k_step_aa_odd(S* __restrict__ A,
+                                                     StepArgs<typename Store<S>::C> p)
+{
+    using C = typename Store<S>::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x, y, z;
+    if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
+    if (WALLS && is_solid(p.g, x, y, z)) return;
+    const unsigned N = p.g.N;
+    const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
+    unsigned idx[Q];
+    bool wall[Q];
+    link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
+    size_t off[Q];
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr int abar = Lattice<D>::opp(a);
+        off[a] = (WALLS && wall[a]) ? size_t(a) * N + own : size_t(abar) * N + idx[a];
+    });
+    C f[Q];
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        f[a] = Store<S>::load(A[off[a]]);
+    });
+    collide<D, C, FORCE>(f, p.c);
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        A[off[Lattice<D>::opp(a)]] = Store<S>::save(f[a]);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// State import / export and moments.  These run on set-up and monitor steps
+// only; they take the canonical FP64 f^n ([Q][N]) through the bijection of
+// gather_offset.
+
+struct IoArgs {
+    Dims g;
+    int bx_shift;
+    int mode;  // GatherMode of the stored state
+    double F[3];
+};
+
+// f^n from equilibrium (rho, u) plus optional noise, or from f (when f is
+// non-null), written into the stored state.  Deviation storages store f - w.
+template <int D, class S, bool WALLS>
+__global__ __launch_bounds__(256) void k_import(S* __restrict__ A, const double* __restrict__ f,
+                                                const double* __restrict__ rho,
+                                                const double* __restrict__ u,
+                                                const double* __restrict__ noise, IoArgs p)
+{
+    constexpr int Q = Lattice<D>::Q;
+    int x, y, z;
+    if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
+    const unsigned N = p.g.N;
+    const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
+    if (WALLS && is_solid(p.g, x, y, z)) return;
+    unsigned idx[Q];
+    bool wall[Q];
+    link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
+    double fn[Q];
+    if (f) {
+        static_for<Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            fn[a] = f[size_t(a) * N + own];
+        });
+    } else {
+        const double r = rho[own];
+        const double ux = u[own], uy = u[size_t(N) + own], uz = D == 3 ? u[2 * size_t(N) + own] : 0.0;
+        const double usq = ux * ux + uy * uy + uz * uz;
+        static_for<Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            constexpr auto& L = kLattice<D>;
+            const double edu = eterm<L.e[a][0]>(ux) + eterm<L.e[a][1]>(uy) + eterm<L.e[a][2]>(uz);
+            double v = L.w[a] * (r + (3.0 * edu + 4.5 * edu * edu - 1.5 * usq));
+            if (noise) v += noise[size_t(a) * N + own];
+            fn[a] = v;
+        });
+    }
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        double v = fn[a];
+        if constexpr (Store<S>::kDeviation) v -= kLattice<D>.w[a];
+        A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], N)] =
+            Store<S>::save(typename Store<S>::C(v));
+    });
+}
+
+// Gathers f^n (in the storage's arithmetic type, as stored: f or f - w).
+template <int D, class S, bool WALLS>
+__device__ __forceinline__ void gather_node(const S* __restrict__ A, const IoArgs& p, int x, int y,
+                                            int z, unsigned own,
+                                            typename Store<S>::C (&f)[Lattice<D>::Q])
+{
+    constexpr int Q = Lattice<D>::Q;
+    unsigned idx[Q];
+    bool wall[Q];
+    link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        f[a] = Store<S>::load(A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.N)]);
+    });
+}
+
+template <int D, class S, bool WALLS>
+__global__ __launch_bounds__(256) void k_export(const S* __restrict__ A, double* __restrict__ f,
+                                                IoArgs p)
+{
+    constexpr int Q = Lattice<D>::Q;
+    int x, y, z;
+    if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
+    const unsigned N = p.g.N;
+    const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
+    if (WALLS && is_solid(p.g, x, y, z)) {
+        for (int a = 0; a < Q; ++a) f[size_t(a) * N + own] = 0.0;
+        return;
+    }
+    typename Store<S>::C fn[Q];
+    gather_node<D, S, WALLS>(A, p, x, y, z, own, fn);
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        double v = double(fn[a]);
+        if constexpr (Store<S>::kDeviation) v += kLattice<D>.w[a];
+        f[size_t(a) * N + own] = v;
+    });
+}
+
+// PostProcessing: rho = sum f (= 1 + sum (f - w) for deviation storage),
+// u = sum e f + F/2.
+template <int D, class S, bool WALLS, class O>
+__global__ __launch_bounds__(256) void k_moments(const S* __restrict__ A, O* __restrict__ rho,
+                                                 O* __restrict__ u, IoArgs p)
+{
+    using C = typename Store<S>::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x, y, z;
+    if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
+    const unsigned N = p.g.N;
+    const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
+    if (WALLS && is_solid(p.g, x, y, z)) {
+        if (rho) rho[own] = O(0);
+        if (u) u[own] = u[size_t(N) + own] = u[2 * size_t(N) + own] = O(0);
+        return;
+    }
+    C fn[Q];
+    gather_node<D, S, WALLS>(A, p, x, y, z, own, fn);
+    const C F[3] = {C(p.F[0]), C(p.F[1]), C(p.F[2])};
+    const Moments<D, C> m = node_moments<D, C, true>(fn, F);
+    if (rho) rho[own] = O(Store<S>::kDeviation ? 1.0 + double(m.rho) : double(m.rho));
+    if (u) {
+        u[own] = O(m.ux);
+        u[size_t(N) + own] = O(m.uy);
+        u[2 * size_t(N) + own] = O(m.uz);
+    }
+}
+
+// Monitor: per-block FP64 partials (sum rho - rho_ref, sum |u|^2, max |u|,
+// non-finite count) over a fixed grid-stride assignment and a fixed
+// in-block tree, so the result is independent of scheduling.
+constexpr int kReduceThreads = 256;
+constexpr int kReduceBlocks = 1024;
+
+template <int D, class S, bool WALLS>
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const S* __restrict__ A,
+                                                                    double* __restrict__ partials,
+                                                                    IoArgs p)
+{
+    using C = typename Store<S>::C;
+    constexpr int Q = Lattice<D>::Q;
+    __shared__ double s_mass[kReduceThreads], s_ke[kReduceThreads], s_max[kReduceThreads],
+        s_bad[kReduceThreads], s_cnt[kReduceThreads];
+    double mass = 0.0, ke = 0.0, umax = 0.0, bad = 0.0, cnt = 0.0;
+    const unsigned N = p.g.N;
+    const C F[3] = {C(p.F[0]), C(p.F[1]), C(p.F[2])};
+    for (unsigned n = blockIdx.x * kReduceThreads + threadIdx.x; n < N;
+         n += kReduceBlocks * kReduceThreads) {
+        const int x = int(n % unsigned(p.g.nx));
+        const unsigned yz = n / unsigned(p.g.nx);
+        const int y = int(yz % unsigned(p.g.ny));
+        const int z = int(yz / unsigned(p.g.ny));
+        if (WALLS && is_solid(p.g, x, y, z)) continue;
+        C fn[Q];
+        gather_node<D, S, WALLS>(A, p, x, y, z, n, fn);
+        for (int a = 0; a < Q; ++a)
+            if (!isfinite(double(fn[a]))) bad += 1.0;
+        const Moments<D, C> m = node_moments<D, C, true>(fn, F);
+        const double ux = m.ux, uy = m.uy, uz = m.uz;
+        const double u2 = ux * ux + uy * uy + uz * uz;
+        mass += double(m.rho);
+        ke += u2;
+        umax = fmax(umax, sqrt(u2));
+        cnt += 1.0;
+    }
+    const int t = threadIdx.x;
+    s_mass[t] = mass;
+    s_ke[t] = ke;
+    s_max[t] = umax;
+    s_bad[t] = bad;
+    s_cnt[t] = cnt;
+    __syncthreads();
+    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            s_mass[t] += s_mass[t + h];
+            s_ke[t] += s_ke[t + h];
+            s_max[t] = fmax(s_max[t], s_max[t + h]);
+            s_bad[t] += s_bad[t + h];
+            s_cnt[t] += s_cnt[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double* o = partials + 5 * size_t(blockIdx.x);
+        o[0] = s_mass[0];
+        o[1] = s_ke[0];
+        o[2] = s_max[0];
+        o[3] = s_bad[0];
+        o[4] = s_cnt[0];
+    }
+}
+
+// Sums the block partials in block order with one block; out[0..3] = mass
+// (plus the fluid-node count for deviation storage), kinetic energy
+// (rho0/2) sum |u|^2, max |u|, non-finite count.
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partials,
+                                                                 int nblocks, int deviation,
+                                                                 double* __restrict__ out)
+{
+    __shared__ double s[5][kReduceThreads];
+    const int t = threadIdx.x;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = t; b < nblocks; b += kReduceThreads) {
+        const double* o = partials + 5 * size_t(b);
+        acc[0] += o[0];
+        acc[1] += o[1];
+        acc[2] = fmax(acc[2], o[2]);
+        acc[3] += o[3];
+        acc[4] += o[4];
+    }
+    for (int k = 0; k < 5; ++k) s[k][t] = acc[k];
+    __syncthreads();
+    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            s[0][t] += s[0][t + h];
+            s[1][t] += s[1][t + h];
+            s[2][t] = fmax(s[2][t], s[2][t + h]);
+            s[3][t] += s[3][t + h];
+            s[4][t] += s[4][t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = deviation ? s[0][0] + s[4][0] : s[0][0];
+        out[1] = 0.5 * s[1][0];
+        out[2] = s[2][0];
+        out[3] = s[3][0];
+    }
+}
+
+}  // namespace imexlbm

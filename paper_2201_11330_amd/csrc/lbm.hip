@@ -1,0 +1,517 @@
+// liblbm.so: host runtime and C interface (include/lbm.h) of the gfx950 LBM
+// time step.  Validates arguments, owns the context, picks the kernel
+// instantiation (lattice x storage x walls x force) and launches it on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+
+using namespace imexlbm;
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+lbm_status fail(lbm_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+lbm_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define LBM_HIP(call)                                      \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+    } while (0)
+
+size_t storage_size(lbm_storage s)
+{
+    switch (s) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    case LBM_F16_DEV:
+    case LBM_BF16_DEV: return 2;
+    }
+    return 0;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_lattice lattice;
+    int D, Q;
+    int nx, ny, nz;
+    unsigned N;
+    double tau, omega;
+    double F[3];
+    int bc[3];
+    lbm_storage storage;
+    unsigned flags;
+    bool walls, force, aa;
+
+    bool bound = false;
+    void* buf[2] = {nullptr, nullptr};
+    int cur = 0;  // AB: buffer holding the current state
+    hipStream_t stream = nullptr;
+    bool state_valid = false;
+    long long steps = 0;
+
+    double* d_partials = nullptr;  // kReduceBlocks * 5 + 4 doubles
+    double* h_result = nullptr;    // 4 doubles, pinned
+
+    int bx_shift = 8;
+    dim3 grid, block;
+};
+
+namespace {
+
+void plan_launch(lbm_ctx* c)
+{
+    int bx = 1, shift = 0;
+    while (bx < c->nx && bx < 256) {
+        bx <<= 1;
+        ++shift;
+    }
+    const int by = 256 / bx;
+    c->bx_shift = shift;
+    c->block = dim3(256, 1, 1);
+    c->grid = dim3((c->nx + bx - 1) / bx, (c->ny + by - 1) / by, c->nz);
+}
+
+Dims dims_of(const lbm_ctx* c)
+{
+    Dims g;
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.nz = c->nz;
+    for (int d = 0; d < 3; ++d) g.bc[d] = c->bc[d];
+    g.N = c->N;
+    return g;
+}
+
+// The gather mode of the current state (AA parity after an odd number of
+// steps means the next step is odd).
+int state_mode(const lbm_ctx* c)
+{
+    if (!c->aa) return kPull;
+    return (c->steps & 1) ? kPullFlip : kLocal;
+}
+
+IoArgs io_args(const lbm_ctx* c)
+{
+    IoArgs p;
+    p.g = dims_of(c);
+    p.bx_shift = c->bx_shift;
+    p.mode = state_mode(c);
+    for (int d = 0; d < 3; ++d) p.F[d] = c->F[d];
+    return p;
+}
+
+template <class C>
+StepArgs<C> step_args(const lbm_ctx* c)
+{
+    StepArgs<C> p;
+    p.g = dims_of(c);
+    p.bx_shift = c->bx_shift;
+    p.c.omega = C(c->omega);
+    for (int d = 0; d < 3; ++d) p.c.F[d] = C(c->F[d]);
+    const double half = 1.0 - 0.5 * c->omega;
+    p.c.k3 = C(3.0 * half);
+    p.c.k9 = C(9.0 * half);
+    return p;
+}
+
+// Kernel instantiations of one lattice and storage.
+template <int D, class S>
+struct Impl {
+    template <bool W, bool F>
+    static void step_ab(lbm_ctx* c, const S* src, S* dst)
+    {
+        hipLaunchKernelGGL((k_step_ab<D, S, W, F>), c->grid, c->block, 0, c->stream, src, dst,
+                           step_args<typename Store<S>::C>(c));
+    }
+    template <bool W, bool F>
+    static void step_aa(lbm_ctx* c, S* A, bool odd)
+    {
+        if (odd)
+            hipLaunchKernelGGL((k_step_aa_odd<D, S, W, F>), c->grid, c->block, 0, c->stream, A,
+                               step_args<typename Store<S>::C>(c));
+        else
+            hipLaunchKernelGGL((k_step_aa_even<D, S, W, F>), c->grid, c->block, 0, c->stream, A,
+                               step_args<typename Store<S>::C>(c));
+    }
+
+    static lbm_status step(lbm_ctx* c, int n)
+    {
+        for (int i = 0; i < n; ++i) {
+            if (c->aa) {
+                S* A = static_cast<S*>(c->buf[0]);
+                const bool odd = c->steps & 1;
+                if (c->walls)
+                    c->force ? step_aa<true, true>(c, A, odd) : step_aa<true, false>(c, A, odd);
+                else
+                    c->force ? step_aa<false, true>(c, A, odd) : step_aa<false, false>(c, A, odd);
+            } else {
+                const S* src = static_cast<const S*>(c->buf[c->cur]);
+                S* dst = static_cast<S*>(c->buf[1 - c->cur]);
+                if (c->walls)
+                    c->force ? step_ab<true, true>(c, src, dst) : step_ab<true, false>(c, src, dst);
+                else
+                    c->force ? step_ab<false, true>(c, src, dst) : step_ab<false, false>(c, src, dst);
+                c->cur = 1 - c->cur;
+            }
+            ++c->steps;
+        }
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    static lbm_status import(lbm_ctx* c, const double* f, const double* rho, const double* u,
+                             const double* noise)
+    {
+        IoArgs p = io_args(c);
+        S* A = static_cast<S*>(c->buf[c->cur]);
+        if (c->walls)
+            hipLaunchKernelGGL((k_import<D, S, true>), c->grid, c->block, 0, c->stream, A, f, rho, u,
+                               noise, p);
+        else
+            hipLaunchKernelGGL((k_import<D, S, false>), c->grid, c->block, 0, c->stream, A, f, rho, u,
+                               noise, p);
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    static lbm_status export_f(lbm_ctx* c, double* f)
+    {
+        IoArgs p = io_args(c);
+        const S* A = static_cast<const S*>(c->buf[c->cur]);
+        if (c->walls)
+            hipLaunchKernelGGL((k_export<D, S, true>), c->grid, c->block, 0, c->stream, A, f, p);
+        else
+            hipLaunchKernelGGL((k_export<D, S, false>), c->grid, c->block, 0, c->stream, A, f, p);
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    template <class O>
+    static void moments_t(lbm_ctx* c, O* rho, O* u)
+    {
+        IoArgs p = io_args(c);
+        const S* A = static_cast<const S*>(c->buf[c->cur]);
+        if (c->walls)
+            hipLaunchKernelGGL((k_moments<D, S, true, O>), c->grid, c->block, 0, c->stream, A, rho, u,
+                               p);
+        else
+            hipLaunchKernelGGL((k_moments<D, S, false, O>), c->grid, c->block, 0, c->stream, A, rho,
+                               u, p);
+    }
+
+    static lbm_status moments(lbm_ctx* c, void* rho, void* u, int f32)
+    {
+        if (f32)
+            moments_t<float>(c, static_cast<float*>(rho), static_cast<float*>(u));
+        else
+            moments_t<double>(c, static_cast<double*>(rho), static_cast<double*>(u));
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    static lbm_status reduce(lbm_ctx* c)
+    {
+        IoArgs p = io_args(c);
+        const S* A = static_cast<const S*>(c->buf[c->cur]);
+        if (c->walls)
+            hipLaunchKernelGGL((k_reduce_partials<D, S, true>), dim3(kReduceBlocks),
+                               dim3(kReduceThreads), 0, c->stream, A, c->d_partials, p);
+        else
+            hipLaunchKernelGGL((k_reduce_partials<D, S, false>), dim3(kReduceBlocks),
+                               dim3(kReduceThreads), 0, c->stream, A, c->d_partials, p);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, c->stream, c->d_partials,
+                           kReduceBlocks, int(Store<S>::kDeviation),
+                           c->d_partials + 5 * size_t(kReduceBlocks));
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+};
+
+// Calls Impl<D, S>::fn(c, args...) for the context's lattice and storage.
+#define LBM_DISPATCH(c, CALL)                                                    \
+    do {                                                                         \
+        if ((c)->D == 2) {                                                       \
+            switch ((c)->storage) {                                              \
+            case LBM_F64: { using I = Impl<2, double>; return I::CALL; }         \
+            case LBM_F32: { using I = Impl<2, float>; return I::CALL; }          \
+            case LBM_F16_DEV: { using I = Impl<2, __half>; return I::CALL; }     \
+            case LBM_BF16_DEV: { using I = Impl<2, __hip_bfloat16>; return I::CALL; } \
+            }                                                                    \
+        } else {                                                                 \
+            switch ((c)->storage) {                                              \
+            case LBM_F64: { using I = Impl<3, double>; return I::CALL; }         \
+            case LBM_F32: { using I = Impl<3, float>; return I::CALL; }          \
+            case LBM_F16_DEV: { using I = Impl<3, __half>; return I::CALL; }     \
+            case LBM_BF16_DEV: { using I = Impl<3, __hip_bfloat16>; return I::CALL; } \
+            }                                                                    \
+        }                                                                        \
+        return fail(LBM_EINVAL, "unknown lattice/storage");                      \
+    } while (0)
+
+lbm_status need_bound(const lbm_ctx* c)
+{
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (!c->bound) return fail(LBM_ENOTBOUND, "context has no buffers bound (lbm_bind)");
+    return LBM_OK;
+}
+
+lbm_status need_state(const lbm_ctx* c)
+{
+    lbm_status st = need_bound(c);
+    if (st) return st;
+    if (!c->state_valid)
+        return fail(LBM_ESTATE, "populations not initialised (lbm_init_equilibrium / lbm_set_populations)");
+    return LBM_OK;
+}
+
+lbm_status check_device_ptr(const void* p, const char* name, bool allow_null)
+{
+    if (!p) return allow_null ? LBM_OK : fail(LBM_EINVAL, "%s is NULL", name);
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBM_EINVAL, "%s is not a HIP allocation", name);
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(LBM_EINVAL, "%s is not device memory", name);
+    int dev = -1;
+    LBM_HIP(hipGetDevice(&dev));
+    if (attr.device != dev) return fail(LBM_EINVAL, "%s is on device %d, current is %d", name, attr.device, dev);
+    return LBM_OK;
+}
+
+lbm_status import_any(lbm_ctx* c, const double* f, const double* rho, const double* u,
+                      const double* noise)
+{
+    LBM_DISPATCH(c, import(c, f, rho, u, noise));
+}
+
+lbm_status reduce_launch(lbm_ctx* c)
+{
+    LBM_DISPATCH(c, reduce(c));
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz, double tau,
+                      const double force[3], const lbm_bc* bc, lbm_storage storage, unsigned flags)
+{
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(LBM_EINVAL, "unknown lattice %d", int(lattice));
+    if (storage_size(storage) == 0) return fail(LBM_EINVAL, "unknown storage %d", int(storage));
+    if (flags & ~unsigned(LBM_FLAG_AA)) return fail(LBM_EINVAL, "unknown flags 0x%x", flags);
+    const int n[3] = {nx, ny, nz};
+    int b[3] = {LBM_PERIODIC, LBM_PERIODIC, LBM_PERIODIC};
+    if (bc)
+        for (int d = 0; d < 3; ++d) b[d] = bc->axis[d];
+    double F[3] = {0.0, 0.0, 0.0};
+    if (force)
+        for (int d = 0; d < 3; ++d) F[d] = force[d];
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] < 1 || n[d] > 65535) return fail(LBM_EINVAL, "dimension %d = %d outside [1, 65535]", d, n[d]);
+        if (b[d] != LBM_PERIODIC && b[d] != LBM_SOLID_ENDS && b[d] != LBM_WALLS_OUTSIDE)
+            return fail(LBM_EINVAL, "unknown boundary %d on axis %d", b[d], d);
+        if (b[d] == LBM_SOLID_ENDS && n[d] < 3)
+            return fail(LBM_EINVAL, "axis %d has solid ends and needs >= 3 nodes", d);
+        if (!std::isfinite(F[d])) return fail(LBM_EINVAL, "force component %d is not finite", d);
+    }
+    if (lattice == LBM_D2Q9 && (nz != 1 || b[2] != LBM_PERIODIC || F[2] != 0.0))
+        return fail(LBM_EINVAL, "D2Q9 needs nz = 1, periodic z and F_z = 0");
+    if (!(tau > 0.5)) return fail(LBM_EINVAL, "tau = %g must exceed 1/2", tau);
+    const bool has_force = F[0] != 0.0 || F[1] != 0.0 || F[2] != 0.0;
+    if (std::isinf(tau) && has_force) return fail(LBM_EINVAL, "tau = inf (pure streaming) needs F = 0");
+    const unsigned long long N = (unsigned long long)nx * ny * nz;
+    if (N >= (1ull << 31)) return fail(LBM_EINVAL, "nx*ny*nz = %llu must be < 2^31", N);
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_EINVAL, "out of host memory");
+    c->lattice = lattice;
+    c->D = lattice == LBM_D2Q9 ? 2 : 3;
+    c->Q = lattice == LBM_D2Q9 ? 9 : 19;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->N = unsigned(N);
+    c->tau = tau;
+    c->omega = 1.0 / tau;
+    for (int d = 0; d < 3; ++d) {
+        c->F[d] = F[d];
+        c->bc[d] = b[d];
+    }
+    c->storage = storage;
+    c->flags = flags;
+    c->aa = flags & LBM_FLAG_AA;
+    c->walls = b[0] != LBM_PERIODIC || b[1] != LBM_PERIODIC || b[2] != LBM_PERIODIC;
+    c->force = has_force;
+    plan_launch(c);
+    *out = c;
+    return LBM_OK;
+}
+
+size_t lbm_buffer_bytes(const lbm_ctx* c)
+{
+    if (!c) return 0;
+    return size_t(c->Q) * c->N * storage_size(c->storage);
+}
+
+lbm_status lbm_bind(lbm_ctx* c, void* buf_a, void* buf_b, void* hip_stream)
+{
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (c->bound) return fail(LBM_ESTATE, "context already bound");
+    lbm_status st = check_device_ptr(buf_a, "buf_a", false);
+    if (st) return st;
+    if (c->aa) {
+        if (buf_b) return fail(LBM_EINVAL, "buf_b must be NULL with LBM_FLAG_AA");
+    } else {
+        st = check_device_ptr(buf_b, "buf_b", false);
+        if (st) return st;
+        if (buf_a == buf_b) return fail(LBM_EINVAL, "buf_a and buf_b are the same buffer");
+    }
+    if ((reinterpret_cast<uintptr_t>(buf_a) | reinterpret_cast<uintptr_t>(buf_b)) & 255)
+        return fail(LBM_EINVAL, "population buffers must be 256-byte aligned");
+    LBM_HIP(hipMalloc(&c->d_partials, sizeof(double) * (5 * size_t(kReduceBlocks) + 4)));
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->h_result), 4 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipFree(c->d_partials);
+        c->d_partials = nullptr;
+        return hip_fail(e, "hipHostMalloc");
+    }
+    c->buf[0] = buf_a;
+    c->buf[1] = buf_b;
+    c->cur = 0;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->bound = true;
+    c->state_valid = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_equilibrium(lbm_ctx* c, const double* rho, const double* u, const double* noise)
+{
+    lbm_status st = need_bound(c);
+    if (st) return st;
+    if ((st = check_device_ptr(rho, "rho", false))) return st;
+    if ((st = check_device_ptr(u, "u", false))) return st;
+    if ((st = check_device_ptr(noise, "noise", true))) return st;
+    c->steps = 0;
+    c->cur = 0;
+    c->state_valid = false;
+    if ((st = import_any(c, nullptr, rho, u, noise))) return st;
+    c->state_valid = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const double* f)
+{
+    lbm_status st = need_bound(c);
+    if (st) return st;
+    if ((st = check_device_ptr(f, "f", false))) return st;
+    c->steps = 0;
+    c->cur = 0;
+    c->state_valid = false;
+    if ((st = import_any(c, f, nullptr, nullptr, nullptr))) return st;
+    c->state_valid = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, double* f)
+{
+    lbm_status st = need_state(c);
+    if (st) return st;
+    if ((st = check_device_ptr(f, "f", false))) return st;
+    LBM_DISPATCH(c, export_f(c, f));
+}
+
+lbm_status lbm_step(lbm_ctx* c, int n)
+{
+    lbm_status st = need_state(c);
+    if (st) return st;
+    if (n < 0) return fail(LBM_EINVAL, "n = %d < 0", n);
+    LBM_DISPATCH(c, step(c, n));
+}
+
+lbm_status lbm_moments(lbm_ctx* c, void* rho, void* u, int out_is_f32)
+{
+    lbm_status st = need_state(c);
+    if (st) return st;
+    if ((st = check_device_ptr(rho, "rho", true))) return st;
+    if ((st = check_device_ptr(u, "u", true))) return st;
+    if (!rho && !u) return LBM_OK;
+    LBM_DISPATCH(c, moments(c, rho, u, out_is_f32));
+}
+
+lbm_status lbm_reduce(lbm_ctx* c, double* mass, double* kinetic_energy, double* umax)
+{
+    lbm_status st = need_state(c);
+    if (st) return st;
+    if ((st = reduce_launch(c))) return st;
+    LBM_HIP(hipMemcpyAsync(c->h_result, c->d_partials + 5 * size_t(kReduceBlocks), 4 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    if (mass) *mass = c->h_result[0];
+    if (kinetic_energy) *kinetic_energy = c->h_result[1];
+    if (umax) *umax = c->h_result[2];
+    if (c->h_result[3] != 0.0 || !std::isfinite(c->h_result[0]) || !std::isfinite(c->h_result[1]))
+        return fail(LBM_EUNSTABLE, "%.0f non-finite populations", c->h_result[3]);
+    return LBM_OK;
+}
+
+long long lbm_steps_taken(const lbm_ctx* c) { return c ? c->steps : -1; }
+
+lbm_status lbm_destroy(lbm_ctx* c)
+{
+    if (!c) return LBM_OK;
+    lbm_status st = LBM_OK;
+    if (c->d_partials) {
+        hipError_t e = hipFree(c->d_partials);
+        if (e != hipSuccess) st = hip_fail(e, "hipFree");
+    }
+    if (c->h_result) {
+        hipError_t e = hipHostFree(c->h_result);
+        if (e != hipSuccess) st = hip_fail(e, "hipHostFree");
+    }
+    delete c;
+    return st;
+}
+
+const char* lbm_status_string(lbm_status s)
+{
+    switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOTBOUND: return "no buffers bound";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_EUNSTABLE: return "non-finite populations";
+    case LBM_ESTATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* lbm_last_error(void) { return g_last_error; }
+
+}  // extern "C"

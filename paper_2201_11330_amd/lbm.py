@@ -1,0 +1,211 @@
+"""ctypes binding of liblbm.so (include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  PyTorch supplies device memory (tensors) and the stream.
+If the library is missing the import of a binding call raises; there is no
+other code path.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+# Enumerations of lbm.h.
+D2Q9, D3Q19 = 0, 1
+PERIODIC, SOLID_ENDS, WALLS_OUTSIDE = 0, 1, 2
+F64, F32, F16_DEV, BF16_DEV = 0, 1, 2, 3
+FLAG_AA = 1
+OK, EINVAL, ENOTBOUND, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
+
+STORAGE_NAMES = {"f64": F64, "f32": F32, "f16": F16_DEV, "bf16": BF16_DEV}
+Q_OF = {D2Q9: 9, D3Q19: 19}
+
+# Every symbol include/lbm.h declares.
+EXPORTS = (
+    "lbm_create", "lbm_buffer_bytes", "lbm_bind", "lbm_init_equilibrium",
+    "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments", "lbm_reduce",
+    "lbm_steps_taken", "lbm_destroy", "lbm_status_string", "lbm_last_error",
+)
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status, where, detail):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+class _BC(ctypes.Structure):
+    _fields_ = [("axis", ctypes.c_int * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liblbm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                           "(python -m paper_2201_11330_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    st = ctypes.c_int
+    L.lbm_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, ctypes.c_double, dp, ctypes.POINTER(_BC), ctypes.c_int,
+                             ctypes.c_uint]
+    L.lbm_create.restype = st
+    L.lbm_buffer_bytes.argtypes = [vp]
+    L.lbm_buffer_bytes.restype = ctypes.c_size_t
+    L.lbm_bind.argtypes = [vp, vp, vp, vp]
+    L.lbm_bind.restype = st
+    L.lbm_init_equilibrium.argtypes = [vp, vp, vp, vp]
+    L.lbm_init_equilibrium.restype = st
+    L.lbm_set_populations.argtypes = [vp, vp]
+    L.lbm_set_populations.restype = st
+    L.lbm_get_populations.argtypes = [vp, vp]
+    L.lbm_get_populations.restype = st
+    L.lbm_step.argtypes = [vp, ctypes.c_int]
+    L.lbm_step.restype = st
+    L.lbm_moments.argtypes = [vp, vp, vp, ctypes.c_int]
+    L.lbm_moments.restype = st
+    L.lbm_reduce.argtypes = [vp, dp, dp, dp]
+    L.lbm_reduce.restype = st
+    L.lbm_steps_taken.argtypes = [vp]
+    L.lbm_steps_taken.restype = ctypes.c_longlong
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_destroy.restype = st
+    L.lbm_status_string.argtypes = [ctypes.c_int]
+    L.lbm_status_string.restype = ctypes.c_char_p
+    L.lbm_last_error.argtypes = []
+    L.lbm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(status, where):
+    if status != OK:
+        detail = lib().lbm_last_error().decode(errors="replace")
+        raise LBMError(status, where, detail or lib().lbm_status_string(status).decode())
+    return status
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev_f64(t, shape, device):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        t = torch.from_numpy(np.require(t, dtype=np.float64, requirements=["C", "W"]))
+    t = t.to(device=device, dtype=torch.float64)
+    return t.reshape(shape).contiguous()
+
+
+class LBM:
+    """One lattice Boltzmann state on one GPU.
+
+    ``tau`` is the lattice relaxation time (omega = 1/tau, nu = (tau - 1/2)/3);
+    ``bc`` gives PERIODIC / SOLID_ENDS / WALLS_OUTSIDE per axis (x, y, z);
+    ``storage`` is "f64", "f32", "f16" or "bf16"; ``aa`` selects the in-place
+    AA pattern.  Launches go to ``stream`` (default: torch's current stream
+    at construction time).
+    """
+
+    def __init__(self, lattice, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), bc=(0, 0, 0),
+                 storage="f64", aa=False, device=None, stream=None):
+        L = lib()
+        self.lattice = lattice
+        self.Q = Q_OF[lattice]
+        self.dims = (nx, ny, nz)
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+        self.tau = float(tau)
+        self.force = tuple(float(v) for v in force)
+        self.bc = tuple(int(b) for b in bc)
+        self.storage = STORAGE_NAMES[storage] if isinstance(storage, str) else int(storage)
+        self.aa = bool(aa)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        F = (ctypes.c_double * 3)(*self.force)
+        bcs = _BC((ctypes.c_int * 3)(*self.bc))
+        check(L.lbm_create(ctypes.byref(h), lattice, nx, ny, nz, self.tau, F, ctypes.byref(bcs),
+                           self.storage, FLAG_AA if self.aa else 0), "lbm_create")
+        self._h = h
+        nbytes = L.lbm_buffer_bytes(h)
+        self.buffers = [torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+                        for _ in range(1 if self.aa else 2)]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        check(L.lbm_bind(h, _ptr(self.buffers[0]), _ptr(self.buffers[1]) if not self.aa else None,
+                         ctypes.c_void_p(self.stream.cuda_stream)), "lbm_bind")
+
+    # -- life cycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- state --------------------------------------------------------------
+    def init_equilibrium(self, rho, u, noise=None):
+        rho = _dev_f64(rho, self.shape, self.device)
+        u = _dev_f64(u, (3,) + self.shape, self.device)
+        noise = _dev_f64(noise, (self.Q,) + self.shape, self.device)
+        self._keep = (rho, u, noise)  # alive until the stream has consumed them
+        check(lib().lbm_init_equilibrium(self._h, _ptr(rho), _ptr(u), _ptr(noise)),
+              "lbm_init_equilibrium")
+
+    def set_populations(self, f):
+        f = _dev_f64(f, (self.Q,) + self.shape, self.device)
+        self._keep = (f,)
+        check(lib().lbm_set_populations(self._h, _ptr(f)), "lbm_set_populations")
+
+    def get_populations(self):
+        f = torch.empty((self.Q,) + self.shape, dtype=torch.float64, device=self.device)
+        check(lib().lbm_get_populations(self._h, _ptr(f)), "lbm_get_populations")
+        return f
+
+    def step(self, n=1):
+        check(lib().lbm_step(self._h, int(n)), "lbm_step")
+
+    @property
+    def steps_taken(self):
+        return lib().lbm_steps_taken(self._h)
+
+    def moments(self, dtype=torch.float64, rho=None, u=None):
+        """(rho, u) of the current state: rho = sum f, u = sum e f + F/2."""
+        if rho is None:
+            rho = torch.empty(self.shape, dtype=dtype, device=self.device)
+        if u is None:
+            u = torch.empty((3,) + self.shape, dtype=dtype, device=self.device)
+        check(lib().lbm_moments(self._h, _ptr(rho), _ptr(u), 1 if dtype == torch.float32 else 0),
+              "lbm_moments")
+        return rho, u
+
+    def reduce(self):
+        """Monitor: {'mass', 'ke', 'umax'} in FP64 (synchronises the stream)."""
+        m, k, um = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        st = lib().lbm_reduce(self._h, ctypes.byref(m), ctypes.byref(k), ctypes.byref(um))
+        out = {"mass": m.value, "ke": k.value, "umax": um.value,
+               "unstable": st == EUNSTABLE}
+        if st not in (OK, EUNSTABLE):
+            check(st, "lbm_reduce")
+        return out

@@ -1,0 +1,282 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle on the
+same seeded inputs.  FP64 bar: relative error <= 1e-12 after N steps
+(max |f_gpu - f_oracle| / max |f_oracle|, and the same for u), the paper's
+own CPU-vs-GPU methodology (Sec. 5).  Permutation-only work (pure
+streaming, state import/export, AA vs AB, translation) is compared bit for
+bit."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2201_11330_amd import lbm
+from paper_2201_11330_amd import workloads as W
+from parity_utils import (inputs, quantize, rel_err, run_gpu, run_oracle, sampled_window_check,
+                          ulp)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _case_id(c):
+    return "x".join(map(str, c[1])) + f"-bc{''.join(map(str, c[3]))}"
+
+
+CASES_3D = [
+    # lattice, dims, tau, bc, force, steps, input kind
+    (W.D3Q19, (37, 29, 23), 0.6, (0, 0, 0), (0, 0, 0), 20, "tg"),
+    (W.D3Q19, (300, 7, 5), 0.7, (0, 0, 0), (2e-6, -1e-6, 1e-6), 12, "tg"),
+    (W.D3Q19, (40, 20, 18), 0.9, (0, 1, 0), (1e-5, 0, 0), 30, "channel"),
+    (W.D3Q19, (33, 17, 12), 0.75, (2, 1, 2), (1e-5, 2e-6, -3e-6), 25, "channel"),
+    (W.D3Q19, (1, 34, 1), 0.9, (0, 1, 0), (1e-5, 0, 0), 60, "channel"),
+    (W.D3Q19, (5, 3, 4), 0.8, (0, 1, 0), (1e-5, 0, 1e-6), 9, "channel"),
+    (W.D3Q19, (1, 1, 1), 0.8, (0, 0, 0), (1e-5, 0, 0), 5, "channel"),
+    (W.D3Q19, (9, 11, 13), 0.55, (1, 1, 1), (1e-5, -1e-5, 1e-5), 15, "channel"),
+    (W.D2Q9, (70, 33, 1), 0.8, (0, 1, 0), (1e-5, 0, 0), 40, "channel"),
+    (W.D2Q9, (300, 45, 1), 1.2, (2, 0, 0), (0, 1e-5, 0), 30, "channel"),
+    (W.D2Q9, (64, 64, 1), 0.8, (0, 0, 0), (0, 0, 0), 50, "tg"),
+]
+
+
+@pytest.mark.parametrize("aa", [False, True], ids=["AB", "AA"])
+@pytest.mark.parametrize("case", CASES_3D, ids=_case_id)
+def test_fp64_parity_against_oracle(case, aa):
+    lattice, dims, tau, bc, force, steps, kind = case
+    rho, u, noise = inputs(lattice, dims, kind, seed=3, noise_amp=1e-5, bc=bc, U0=0.03)
+    f_or, r_or, u_or, red_or = run_oracle(lattice, dims, tau, force, bc, rho, u, noise, steps)
+    f, r, v, red = run_gpu(lattice, dims, tau, force, bc, rho, u, noise, steps, aa=aa)
+    ef, eu, er = rel_err(f, f_or), rel_err(v, u_or), rel_err(r, r_or)
+    print(f"{dims} bc={bc} aa={aa}: f {ef:.2e} u {eu:.2e} rho {er:.2e}")
+    assert ef <= TOL and eu <= TOL and er <= TOL
+    assert abs(red["mass"] - red_or["mass"]) <= TOL * abs(red_or["mass"])
+    assert abs(red["ke"] - red_or["ke"]) <= 1e-10 * red_or["ke"]
+    assert abs(red["umax"] - red_or["umax"]) <= TOL * red_or["umax"]
+    assert not red["unstable"]
+
+
+@pytest.mark.parametrize("aa", [False, True], ids=["AB", "AA"])
+def test_taylor_green_2d_full_workload(aa):
+    """Workload D2Q9 128^2, tau = 0.8, 1000 steps: parity at every node, and
+    the kinetic energy decay rate 4 nu k^2 of the closed form."""
+    n, tau, steps = 128, 0.8, 1000
+    rho, u = W.taylor_green_2d(n, U0=0.01)
+    f_or, r_or, u_or, red_or = run_oracle(W.D2Q9, (n, n, 1), tau, (0, 0, 0), (0, 0, 0), rho, u,
+                                          None, steps)
+    sim = lbm.LBM(lbm.D2Q9, n, n, 1, tau, aa=aa)
+    sim.init_equilibrium(rho, u)
+    ts, ke = [], []
+    for it in range(steps + 1):
+        if it % 10 == 0 and it >= 100:
+            ts.append(it)
+            ke.append(sim.reduce()["ke"])
+        if it < steps:
+            sim.step(1)
+    f = sim.get_populations().cpu().numpy()
+    _, v = sim.moments()
+    assert rel_err(f, f_or) <= TOL
+    assert rel_err(v.cpu().numpy(), u_or) <= TOL
+    rate = -np.polyfit(np.array(ts, float), np.log(ke), 1)[0]
+    nu, k = (tau - 0.5) / 3, 2 * math.pi / n
+    assert abs(rate / (4 * nu * k * k) - 1) < 1e-4
+    assert abs(ke[-1] - red_or["ke"]) <= 1e-10 * red_or["ke"]
+
+
+@pytest.mark.parametrize("aa", [False, True], ids=["AB", "AA"])
+@pytest.mark.parametrize("lattice,dims", [(W.D3Q19, (6, 6, 6)), (W.D2Q9, (9, 9, 1))])
+def test_pure_streaming_bit_exact(lattice, dims, aa):
+    """tau = inf: each step is the propagation permutation; the GPU equals the
+    oracle bit for bit and n steps on a periodic n-cube are the identity."""
+    nx, ny, nz = dims
+    Q = 19 if lattice == W.D3Q19 else 9
+    f0 = np.random.default_rng(1).uniform(0.0, 0.1, size=(Q, nz, ny, nx))
+    sim = lbm.LBM(lattice, nx, ny, nz, math.inf, aa=aa)
+    sim.set_populations(f0)
+    import oracle
+    ref = oracle.Sim(lattice, nx, ny, nz, tau=math.inf)
+    ref.set_populations(f0)
+    for k in range(1, nx + 1):
+        sim.step(1)
+        ref.step(1)
+        assert np.array_equal(sim.get_populations().cpu().numpy(), ref.get_populations())
+    assert np.array_equal(sim.get_populations().cpu().numpy(), f0)
+
+
+@pytest.mark.parametrize("bc,force", [((0, 0, 0), (0, 0, 0)), ((0, 1, 0), (1e-5, 0, 0)),
+                                      ((2, 1, 1), (1e-5, 1e-6, -1e-6))])
+def test_aa_equals_ab_bitwise(bc, force):
+    """The AA pattern runs the same collision on the same populations, so it
+    matches the two-lattice scheme bit for bit after any number of steps."""
+    dims = (45, 18, 13)
+    rho, u, noise = inputs(W.D3Q19, dims, "channel", seed=4, noise_amp=1e-5, bc=bc, U0=0.03)
+    ab = lbm.LBM(lbm.D3Q19, *dims, 0.7, force=force, bc=bc)
+    aa = lbm.LBM(lbm.D3Q19, *dims, 0.7, force=force, bc=bc, aa=True)
+    for s in (ab, aa):
+        s.init_equilibrium(rho, u, noise)
+    for n in (1, 1, 2, 3, 7):
+        ab.step(n)
+        aa.step(n)
+        assert torch.equal(ab.get_populations(), aa.get_populations())
+        assert torch.equal(ab.moments()[1], aa.moments()[1])
+
+
+def test_translation_equivariance_bitwise():
+    dims = (40, 24, 20)
+    nx, ny, nz = dims
+    rho, u, noise = inputs(W.D3Q19, dims, "tg", noise_amp=1e-5)
+    a = lbm.LBM(lbm.D3Q19, *dims, 0.6, force=(1e-6, 0, 2e-6))
+    a.init_equilibrium(rho, u, noise)
+    f0 = a.get_populations()
+    b = lbm.LBM(lbm.D3Q19, *dims, 0.6, force=(1e-6, 0, 2e-6))
+    shift = (3, 5, 7)
+    b.set_populations(torch.roll(f0, shift, dims=(1, 2, 3)))
+    a.step(6)
+    b.step(6)
+    assert torch.equal(b.get_populations(), torch.roll(a.get_populations(), shift, dims=(1, 2, 3)))
+
+
+@pytest.mark.parametrize("aa", [False, True], ids=["AB", "AA"])
+@pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 0), (2, 2, 1)])
+def test_state_roundtrip_bitwise(aa, bc):
+    """get/set are inverse permutations of the stored state: a state exported
+    after any number of steps (either AA parity) and imported into a fresh
+    context continues bit for bit."""
+    dims = (23, 14, 9)
+    rho, u, noise = inputs(W.D3Q19, dims, "channel", seed=8, noise_amp=1e-5, bc=bc, U0=0.03)
+    a = lbm.LBM(lbm.D3Q19, *dims, 0.8, force=(1e-5, 0, 0), bc=bc, aa=aa)
+    a.init_equilibrium(rho, u, noise)
+    f0 = a.get_populations()
+    a.set_populations(f0)
+    assert torch.equal(a.get_populations(), f0)
+    for n in (1, 2, 3):
+        a.step(n)
+        fa = a.get_populations()
+        b = lbm.LBM(lbm.D3Q19, *dims, 0.8, force=(1e-5, 0, 0), bc=bc, aa=aa)
+        b.set_populations(fa)
+        assert torch.equal(b.get_populations(), fa)
+        a.step(3)
+        b.step(3)
+        assert torch.equal(a.get_populations(), b.get_populations())
+        b.close()
+
+
+def test_full_size_taylor_green_256_sampled():
+    """Workload D3Q19 256^3 FP64 (the benchmark's launch configuration), 6
+    steps: sampled nodes -- including the periodic seams -- against the oracle
+    run on each node's dependency window."""
+    n, steps, tau = 256, 6, 0.6
+    dims = (n, n, n)
+    rho, u = W.taylor_green_3d(n, U0=0.05)
+    noise = W.population_noise(W.D3Q19, dims, 1e-6, seed=2)
+    sim = lbm.LBM(lbm.D3Q19, n, n, n, tau)
+    sim.init_equilibrium(rho, u, noise)
+    sim.step(steps)
+    f = sim.get_populations()
+    _, v = sim.moments()
+    rng = np.random.default_rng(0)
+    centers = [(0, 0, 0), (255, 255, 255), (0, 128, 255), (255, 0, 17), (64, 192, 3)]
+    centers += [tuple(int(c) for c in rng.integers(0, n, 3)) for _ in range(5)]
+    ef, eu = sampled_window_check(f, v, W.D3Q19, dims, tau, (0, 0, 0), (0, 0, 0), rho, u, noise,
+                                  steps, centers)
+    print(f"256^3 sampled: f {ef:.2e} u {eu:.2e}")
+    assert ef <= TOL and eu <= TOL
+    red = sim.reduce()
+    assert not red["unstable"]
+    assert abs(red["mass"] / (rho.sum() + noise.sum()) - 1) < 1e-13
+
+
+def test_full_size_channel_sampled():
+    """Workload D3Q19 channel 512 x 128 x 128, walls at y = 0 and 127, g_x =
+    1e-6, tau = 0.9: sampled columns against the oracle on their dependency
+    window (the full wall-normal extent)."""
+    dims = (512, 128, 128)
+    bc = (W.PERIODIC, W.SOLID_ENDS, W.PERIODIC)
+    steps, tau, force = 4, 0.9, (1e-6, 0, 0)
+    rho, u = W.channel(*dims, amplitude=1e-4, seed=3, bc=bc)
+    sim = lbm.LBM(lbm.D3Q19, *dims, tau, force=force, bc=bc)
+    sim.init_equilibrium(rho, u)
+    sim.step(steps)
+    f = sim.get_populations()
+    _, v = sim.moments()
+    centers = [(0, 1, 0), (511, 126, 127), (255, 64, 64), (100, 2, 3), (7, 125, 90)]
+    ef, eu = sampled_window_check(f, v, W.D3Q19, dims, tau, force, bc, rho, u, None, steps,
+                                  centers)
+    print(f"channel sampled: f {ef:.2e} u {eu:.2e}")
+    assert ef <= TOL and eu <= TOL
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("aa", [False, True], ids=["AB", "AA"])
+def test_reduced_precision_one_step(storage, aa):
+    """Deviation storage: from a state exactly representable in the storage
+    format, one step equals the FP64 oracle's step rounded to the format, to
+    within one unit in the last place of the format plus FP32 arithmetic
+    error."""
+    import oracle
+    dims = (37, 21, 10)
+    bc, force, tau = (0, 1, 0), (1e-5, 0, 0), 0.7
+    rho, u, noise = inputs(W.D3Q19, dims, "channel", seed=9, noise_amp=1e-4, bc=bc, U0=0.04)
+    ref = oracle.Sim(W.D3Q19, *dims, tau=tau, force=force, bc=bc)
+    ref.init_equilibrium(rho, u, noise)
+    fluid = ref.geometry()
+    _, t = oracle.lattice_tables(W.D3Q19)
+    tw = t[:, None, None, None] * fluid
+    g0 = quantize(ref.get_populations() - tw, storage)
+    g0[np.abs(g0) < 1e-8] = 0.0
+    f0 = g0 + tw
+    ref.set_populations(f0)
+    sim = lbm.LBM(lbm.D3Q19, *dims, tau, force=force, bc=bc, storage=storage, aa=aa)
+    sim.set_populations(f0)
+    assert np.array_equal(sim.get_populations().cpu().numpy() - tw, g0)
+    ref.step(1)
+    sim.step(1)
+    g_ref = ref.get_populations() - tw
+    g = sim.get_populations().cpu().numpy() - tw
+    tol = ulp(g_ref, storage) + 64 * np.finfo(np.float32).eps * np.abs(g_ref).max()
+    worst = (np.abs(g - g_ref) / tol).max()
+    print(f"{storage} aa={aa}: worst error / tolerance = {worst:.3f}")
+    assert worst <= 1.0
+
+
+def test_reduce_flags_non_finite():
+    dims = (8, 6, 5)
+    sim = lbm.LBM(lbm.D3Q19, *dims, 0.8)
+    rho, u, _ = inputs(W.D3Q19, dims, "tg", noise_amp=0)
+    sim.init_equilibrium(rho, u)
+    f = sim.get_populations()
+    f[3, 2, 1, 4] = float("nan")
+    sim.set_populations(f)
+    assert sim.reduce()["unstable"]
+    sim.set_populations(torch.nan_to_num(f, nan=1.0 / 36))
+    assert not sim.reduce()["unstable"]
+
+
+def test_error_paths_on_device():
+    sim = lbm.LBM(lbm.D3Q19, 8, 8, 8, 0.8)
+    with pytest.raises(lbm.LBMError) as e:
+        sim.step(1)  # no state yet
+    assert e.value.status == lbm.ESTATE
+    sim.init_equilibrium(np.ones((8, 8, 8)), np.zeros((3, 8, 8, 8)))
+    sim.step(0)
+    assert sim.steps_taken == 0
+    with pytest.raises(lbm.LBMError) as e:
+        sim.step(-1)
+    assert e.value.status == lbm.EINVAL
+    host = torch.zeros((19, 8, 8, 8), dtype=torch.float64)
+    st = lbm.lib().lbm_get_populations(sim._h, host.data_ptr())
+    assert st == lbm.EINVAL  # host pointer rejected before any launch
+
+
+def test_runs_on_a_side_stream():
+    dims = (20, 12, 10)
+    rho, u, noise = inputs(W.D3Q19, dims, "tg", noise_amp=1e-5)
+    ref = run_gpu(W.D3Q19, dims, 0.7, (0, 0, 0), (0, 0, 0), rho, u, noise, 8, reduce=False)[0]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        sim = lbm.LBM(lbm.D3Q19, *dims, 0.7)
+        sim.init_equilibrium(rho, u, noise)
+        sim.step(8)
+        f = sim.get_populations()
+    s.synchronize()
+    assert np.array_equal(f.cpu().numpy(), ref)

@@ -15,6 +15,7 @@ launch duration measured with HIP events on the launch stream, and the CPU
 oracle's MLUPS on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -116,6 +117,31 @@ def run_gpu(n, storage, pattern, steps, warmup, copy_probe=False):
     return result
 
 
+def kernel_sources_sha256():
+    parts = ["paper_2201_11330_amd/csrc/kernels.hpp", "paper_2201_11330_amd/csrc/lattice.hpp",
+             "paper_2201_11330_amd/csrc/lbm.hip"]
+    h = hashlib.sha256()
+    for p in parts:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(storage, pattern, n):
+    """HBM bytes per launch of the timed kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE figures (scaled by a plain copy of known size),
+    or None when no figures exist for this configuration or the kernel
+    sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_step_{pattern}_d3q19_{storage}_{n}cube.counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return d["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(n, target_s):
     """The oracle, as it stands, on the host cores: whole-domain steps of the
     same workload, as many as fit in about target_s seconds."""
@@ -191,7 +217,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.storage, args.pattern, n),
             "kernel": f"k_step_{args.pattern}<D3Q19,{args.storage}>",
             "bytes_per_update": blu,
             "launch_ms_mean": round(r["launch_ms_mean"], 5),

@@ -23,6 +23,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "lattice.hpp"
@@ -109,6 +110,7 @@ struct Dims {
     int nx, ny, nz;
     int bc[3];
     unsigned N;  // nx*ny*nz
+    size_t P;    // elements from one population plane of the stored state to the next (>= N)
 };
 
 // Coordinates c-1, c, c+1 of one axis (index = shift + 1), wrapped on a
@@ -190,13 +192,48 @@ __device__ __forceinline__ void link_nodes(const Dims& g, int x, int y, int z,
 // pairs of fluid nodes and slots.
 template <int D>
 __device__ __forceinline__ size_t gather_offset(int mode, int a, unsigned own, unsigned src,
-                                                bool wall, unsigned N)
+                                                bool wall, size_t P)
 {
     const int abar = Lattice<D>::opp(a);
-    if (mode == kLocal) return size_t(a) * N + own;
-    if (mode == kPull) return wall ? size_t(abar) * N + own : size_t(a) * N + src;
-    return wall ? size_t(a) * N + own : size_t(abar) * N + src;  // kPullFlip
+    if (mode == kLocal) return size_t(a) * P + own;
+    if (mode == kPull) return wall ? size_t(abar) * P + own : size_t(a) * P + src;
+    return wall ? size_t(a) * P + own : size_t(abar) * P + src;  // kPullFlip
 }
+
+// Loads and stores of population elements.  NT marks an access
+// non-temporal (streamed, not kept in the caches): used for every store of
+// a step and for the loads whose cache lines no other lane of the workgroup
+// touches (directions with e_x = 0, whose 64-lane rows are 512-byte
+// aligned).  Loads shifted by one element along x share their boundary
+// lines with the neighbouring wavefront and stay cached.
+template <class S>
+using Bits = std::conditional_t<sizeof(S) == 8, unsigned long long,
+                                std::conditional_t<sizeof(S) == 4, unsigned, unsigned short>>;
+
+template <bool NT, class S>
+__device__ __forceinline__ void put(S* p, S v)
+{
+    if constexpr (NT) {
+        __builtin_nontemporal_store(__builtin_bit_cast(Bits<S>, v), reinterpret_cast<Bits<S>*>(p));
+    } else {
+        *p = v;
+    }
+}
+
+template <bool NT, class S>
+__device__ __forceinline__ S get(const S* p)
+{
+    if constexpr (NT) {
+        return __builtin_bit_cast(S, __builtin_nontemporal_load(reinterpret_cast<const Bits<S>*>(p)));
+    } else {
+        return *p;
+    }
+}
+
+// Workgroups of the step kernels: 256 work-items; the compiler may use up
+// to 128 VGPRs so that all Q loads of a work-item are in flight before the
+// collision (measured faster than forcing 8 waves per SIMD).
+#define LBM_STEP_BOUNDS __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 8)))
 
 // ---------------------------------------------------------------------------
 // Collision at one node (Eq. (collision) with the incompressible equilibrium
@@ -278,8 +315,8 @@ struct StepArgs {
 };
 
 // Fused pull-stream + bounce-back + collide (AB).
-template <int D, class S, bool WALLS, bool FORCE>
-__global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* __restrict__ dst,
+template <int D, class S, bool WALLS, bool FORCE, bool NT>
+__global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restrict__ dst,
                                                  StepArgs<typename Store<S>::C> p)
 {
     using C = typename Store<S>::C;
@@ -287,7 +324,7 @@ __global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* _
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     if (WALLS && is_solid(p.g, x, y, z)) return;
-    const unsigned N = p.g.N;
+    const size_t P = p.g.P;
     const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
     unsigned idx[Q];
     bool wall[Q];
@@ -296,19 +333,20 @@ __global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* _
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         constexpr int abar = Lattice<D>::opp(a);
-        const S v = (WALLS && wall[a]) ? src[size_t(abar) * N + own] : src[size_t(a) * N + idx[a]];
-        f[a] = Store<S>::load(v);
+        constexpr bool aligned = kLattice<D>.e[a][0] == 0;
+        const S* ptr = (WALLS && wall[a]) ? src + size_t(abar) * P + own : src + size_t(a) * P + idx[a];
+        f[a] = Store<S>::load(get<NT && aligned>(ptr));
     });
     collide<D, C, FORCE>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        dst[size_t(a) * N + own] = Store<S>::save(f[a]);
+        put<NT>(dst + size_t(a) * P + own, Store<S>::save(f[a]));
     });
 }
 
 // AA even step: own slots in, opposite own slots out.
-template <int D, class S, bool WALLS, bool FORCE>
-__global__ __launch_bounds__(256) void k_step_aa_even(S* __restrict__ A,
+template <int D, class S, bool WALLS, bool FORCE, bool NT>
+__global__ LBM_STEP_BOUNDS void k_step_aa_even(S* __restrict__ A,
                                                       StepArgs<typename Store<S>::C> p)
 {
     using C = typename Store<S>::C;
@@ -316,25 +354,25 @@ __global__ __launch_bounds__(256) void k_step_aa_even(S* __restrict__ A,
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     if (WALLS && is_solid(p.g, x, y, z)) return;
-    const unsigned N = p.g.N;
+    const size_t P = p.g.P;
     const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
     C f[Q];
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        f[a] = Store<S>::load(A[size_t(a) * N + own]);
+        f[a] = Store<S>::load(get<NT>(A + size_t(a) * P + own));
     });
     collide<D, C, FORCE>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        A[size_t(Lattice<D>::opp(a)) * N + own] = Store<S>::save(f[a]);
+        put<NT>(A + size_t(Lattice<D>::opp(a)) * P + own, Store<S>::save(f[a]));
     });
 }
 
 // AA odd step: f_a(x) from slot abar of x - e_a (or slot a of x at a wall);
 // f*_a(x) goes to slot a of x + e_a (or slot abar of x at a wall), which is
 // the address read for direction abar.
-template <int D, class S, bool WALLS, bool FORCE>
-__global__ __launch_bounds__(256) void k_step_aa_odd(S* __restrict__ A,
+template <int D, class S, bool WALLS, bool FORCE, bool NT>
+__global__ LBM_STEP_BOUNDS void k_step_aa_odd(S* __restrict__ A,
                                                      StepArgs<typename Store<S>::C> p)
 {
     using C = typename Store<S>::C;
@@ -342,7 +380,7 @@ __global__ __launch_bounds__(256) void k_step_aa_odd(S* __restrict__ A,
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     if (WALLS && is_solid(p.g, x, y, z)) return;
-    const unsigned N = p.g.N;
+    const size_t P = p.g.P;
     const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
     unsigned idx[Q];
     bool wall[Q];
@@ -351,17 +389,17 @@ __global__ __launch_bounds__(256) void k_step_aa_odd(S* __restrict__ A,
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         constexpr int abar = Lattice<D>::opp(a);
-        off[a] = (WALLS && wall[a]) ? size_t(a) * N + own : size_t(abar) * N + idx[a];
+        off[a] = (WALLS && wall[a]) ? size_t(a) * P + own : size_t(abar) * P + idx[a];
     });
     C f[Q];
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        f[a] = Store<S>::load(A[off[a]]);
+        f[a] = Store<S>::load(get<NT && kLattice<D>.e[a][0] == 0>(A + off[a]));
     });
     collide<D, C, FORCE>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        A[off[Lattice<D>::opp(a)]] = Store<S>::save(f[a]);
+        put<NT>(A + off[Lattice<D>::opp(a)], Store<S>::save(f[a]));
     });
 }
 
@@ -417,7 +455,7 @@ __global__ __launch_bounds__(256) void k_import(S* __restrict__ A, const double*
         constexpr int a = decltype(ac)::value;
         double v = fn[a];
         if constexpr (Store<S>::kDeviation) v -= kLattice<D>.w[a];
-        A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], N)] =
+        A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.P)] =
             Store<S>::save(typename Store<S>::C(v));
     });
 }
@@ -434,7 +472,7 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ A, const IoArg
     link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        f[a] = Store<S>::load(A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.N)]);
+        f[a] = Store<S>::load(A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.P)]);
     });
 }
 

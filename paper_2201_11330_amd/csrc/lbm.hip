@@ -50,6 +50,12 @@ size_t storage_size(lbm_storage s)
     return 0;
 }
 
+// Non-temporal stores (and unshared loads) in the step kernels.
+constexpr bool kNtStores = true;
+
+// Elements between population planes: N itself.
+size_t plane_stride(unsigned long long N, size_t elem) { (void)elem; return size_t(N); }
+
 }  // namespace
 
 struct lbm_ctx {
@@ -57,6 +63,7 @@ struct lbm_ctx {
     int D, Q;
     int nx, ny, nz;
     unsigned N;
+    size_t P;  // plane stride of the stored state, elements
     double tau, omega;
     double F[3];
     int bc[3];
@@ -101,6 +108,7 @@ Dims dims_of(const lbm_ctx* c)
     g.nz = c->nz;
     for (int d = 0; d < 3; ++d) g.bc[d] = c->bc[d];
     g.N = c->N;
+    g.P = c->P;
     return g;
 }
 
@@ -142,17 +150,17 @@ struct Impl {
     template <bool W, bool F>
     static void step_ab(lbm_ctx* c, const S* src, S* dst)
     {
-        hipLaunchKernelGGL((k_step_ab<D, S, W, F>), c->grid, c->block, 0, c->stream, src, dst,
+        hipLaunchKernelGGL((k_step_ab<D, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, src, dst,
                            step_args<typename Store<S>::C>(c));
     }
     template <bool W, bool F>
     static void step_aa(lbm_ctx* c, S* A, bool odd)
     {
         if (odd)
-            hipLaunchKernelGGL((k_step_aa_odd<D, S, W, F>), c->grid, c->block, 0, c->stream, A,
+            hipLaunchKernelGGL((k_step_aa_odd<D, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, A,
                                step_args<typename Store<S>::C>(c));
         else
-            hipLaunchKernelGGL((k_step_aa_even<D, S, W, F>), c->grid, c->block, 0, c->stream, A,
+            hipLaunchKernelGGL((k_step_aa_even<D, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, A,
                                step_args<typename Store<S>::C>(c));
     }
 
@@ -358,6 +366,7 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
     c->ny = ny;
     c->nz = nz;
     c->N = unsigned(N);
+    c->P = plane_stride(N, storage_size(storage));
     c->tau = tau;
     c->omega = 1.0 / tau;
     for (int d = 0; d < 3; ++d) {
@@ -377,7 +386,7 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
 size_t lbm_buffer_bytes(const lbm_ctx* c)
 {
     if (!c) return 0;
-    return size_t(c->Q) * c->N * storage_size(c->storage);
+    return size_t(c->Q) * c->P * storage_size(c->storage);
 }
 
 lbm_status lbm_bind(lbm_ctx* c, void* buf_a, void* buf_b, void* hip_stream)

@@ -117,6 +117,59 @@ def run_gpu(n, storage, pattern, steps, warmup, copy_probe=False):
     return result
 
 
+def run_adjoint(n=128, steps=500, k=50, storage="f32", tau=0.7):
+    """Adjoint workload: D3Q19 n^3 periodic, random divergence-free start
+    (8 Fourier modes |K| <= 4, amplitude 0.02, seed 11), target from seed 12,
+    J = 1/2 |u^N - u_tgt|^2.  Times the plain forward (lbm_step), the
+    checkpointed forward (lbm_forward_record) and the backward sweep
+    (lbm_adjoint: segment recompute + adjoint steps + init map)."""
+    import torch
+
+    from paper_2201_11330_amd import lbm
+    from paper_2201_11330_amd import workloads as W
+
+    rho, u0 = W.random_fourier_field(n, modes=8, kmax=4, amplitude=0.02, seed=11)
+    _, ut0 = W.random_fourier_field(n, modes=8, kmax=4, amplitude=0.02, seed=12)
+    tgt = lbm.LBM(lbm.D3Q19, n, n, n, tau, storage=storage)
+    tgt.init_equilibrium(rho, ut0)
+    tgt.step(steps)
+    _, u_tgt = tgt.moments()
+    tgt.close()
+    sim = lbm.LBM(lbm.D3Q19, n, n, n, tau, storage=storage)
+    ckpt = torch.empty((steps // k) * sim.buffer_bytes, dtype=torch.uint8, device="cuda")
+    work = torch.empty(lbm.lib().lbm_adjoint_workspace_bytes(sim._h, k), dtype=torch.uint8,
+                       device="cuda")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        out = fn()
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), out
+
+    for _ in range(2):  # second pass is the measured one
+        sim.init_equilibrium(rho, u0)
+        t_plain, _ = timed(lambda: sim.step(steps))
+        sim.init_equilibrium(rho, u0)
+        t_rec, _ = timed(lambda: sim.forward_record(steps, k, ckpt))
+        _, uN = sim.moments()
+        ubar = (uN - u_tgt).contiguous()
+        t_adj, grads = timed(lambda: sim.adjoint(steps, k, ckpt, u0, ubar, work))
+    sim.close()
+    return {
+        "workload": f"D3Q19 {n}^3 periodic, tau={tau}, {steps} steps, checkpoint every {k}, "
+                    f"{storage} storage (f - w), random Fourier start",
+        "forward_ms": round(t_plain, 3),
+        "forward_record_ms": round(t_rec, 3),
+        "backward_ms": round(t_adj, 3),
+        "backward_over_forward": round(t_adj / t_plain, 3),
+        "bytes_model_ratio": 2.5,
+        "dJ_dtau": grads[1],
+    }
+
+
 def kernel_sources_sha256():
     parts = ["paper_2201_11330_amd/csrc/kernels.hpp", "paper_2201_11330_amd/csrc/lattice.hpp",
              "paper_2201_11330_amd/csrc/lbm.hip"]
@@ -235,6 +288,8 @@ def main():
         out["fp16_store"] = {"mlups": round(m16, 1), "speedup_vs_f64": round(m16 / mlups, 3),
                              "achieved_gbs": round(a16, 1),
                              "frac": round(a16 / HBM_PEAK_GBS, 4)}
+    if not args.no_extras and args.storage == "f64":
+        out["adjoint"] = run_adjoint()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -106,7 +106,8 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
                       const double force[3], const lbm_bc* bc, lbm_storage storage,
                       unsigned flags);
 
-/* Bytes of one population buffer: Q * N * sizeof(storage element). */
+/* Bytes of one population buffer: Q planes of N nodes (each plane padded to
+ * a multiple of 128 elements) of the storage element; a multiple of 256. */
 size_t lbm_buffer_bytes(const lbm_ctx* ctx);
 
 /*
@@ -159,6 +160,48 @@ lbm_status lbm_reduce(lbm_ctx* ctx, double* mass, double* kinetic_energy, double
 
 /* Time steps taken since the last init/set (the AA parity is its low bit). */
 long long lbm_steps_taken(const lbm_ctx* ctx);
+
+/*
+ * Discrete adjoint (not in the paper; the reverse-mode derivative of n time
+ * steps).  Forward model: f^0 = feq(rho, u0) (+ noise) by
+ * lbm_init_equilibrium, f^{k+1} = S C(f^k; tau, F) by lbm_step, and the
+ * final velocity u^n = sum_a e_a f^n_a + F/2.  For a scalar J(u^n) the
+ * adjoint returns dJ/du0, dJ/dtau and dJ/dF given dJ/du^n.
+ *
+ * lbm_forward_record advances n steps from the current state like
+ * lbm_step(ctx, n) and stores the state at steps 0, k, 2k, ..., n-k
+ * (relative to the start) in ckpt: n/k consecutive device buffers of
+ * lbm_buffer_bytes() each.  k must divide n.  Two-lattice pattern only
+ * (LBM_EINVAL with LBM_FLAG_AA).  Asynchronous on the bound stream.
+ */
+lbm_status lbm_forward_record(lbm_ctx* ctx, int n, int k, void* ckpt);
+
+/* Device workspace lbm_adjoint needs for checkpoint interval k: k-1 state
+ * buffers for the recomputed segment, two adjoint fields and the FP64
+ * accumulators.  0 for a NULL context or k < 1. */
+size_t lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k);
+
+/*
+ * Backward sweep over the n steps recorded by lbm_forward_record with the
+ * same n and k (ckpt as filled there, unchanged).  Each k-step segment is
+ * recomputed from its checkpoint into the workspace, then k adjoint steps
+ * run backwards: the transposed propagation (a pull from x + e_a, with the
+ * bounce-back links reversed) and the transposed collision Jacobian.  The
+ * segment recompute and the adjoint steps read the stored states; the
+ * context's own buffers and state are not touched.
+ *   u0     [3][N] device FP64: the initial velocity given to
+ *          lbm_init_equilibrium (the init map's linearisation point)
+ *   dJ_du  [3][N] device FP64: dJ/du^n (solid nodes ignored)
+ *   dJ_du0 [3][N] device FP64 output (0 on solid nodes)
+ *   dJ_dtau, dJ_dforce: host outputs (either may be NULL), accumulated in
+ *          FP64 in a fixed order; dJ_dforce[2] = 0 for D2Q9
+ * work: lbm_adjoint_workspace_bytes(ctx, k) bytes of device memory,
+ * 256-byte aligned.  Adjoint fields use the storage's arithmetic type
+ * (FP64 for LBM_F64, FP32 otherwise).  Needs a finite tau and the
+ * two-lattice pattern.  Synchronises the bound stream.
+ */
+lbm_status lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, void* work, const double* u0,
+                       const double* dJ_du, double* dJ_du0, double* dJ_dtau, double dJ_dforce[3]);
 
 /* Frees the context and its scratch (not the caller's buffers).  NULL is a
  * no-op. */

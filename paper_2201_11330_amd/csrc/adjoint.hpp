@@ -1,0 +1,247 @@
+// Discrete adjoint of the LBM time step for gfx950.
+//
+// Forward model (two-lattice state g^n, f^n = S g^n):
+//   f^{n+1} = S C(f^n; tau, F),  u^n = sum_a e_a f^n_a + F/2  (rho0 = 1),
+// with C the node collision and S the propagation with bounce-back, a
+// permutation.  Given lambda^{n+1} = dJ/df^{n+1}, one adjoint step is
+//   lambda*_a(x) = lambda^{n+1}_a(x + e_a)   (lambda^{n+1}_abar(x) at a wall:
+//                                           S^T = S^-1, a pull from x + e_a)
+//   lambda^n     = (dC/df)^T lambda*,  taubar += (dC/dtau)^T lambda*,
+//                                      Fbar   += (dC/dF)^T lambda*.
+// The transposed collision Jacobian has a closed form through four weighted
+// moments of lambda* at the node (w_a weights, u the node velocity):
+//   m0 = sum w l,  m1 = sum w l e,  m2 = sum w l (e.u) e,  m3 = sum w l (e.F) e,
+//   A  = 3 m1 + 9 m2 - 3 m0 u,       B  = 9 m3 - 3 m0 F,
+//   lambda^n_b = (1 - omega) l_b + omega m0 + (omega A + (1 - omega/2) B) . e_b,
+//   taubar    += -omega^2 sum_a l_a (feq_a - f_a - G_a/2),
+//   Fbar      += A + (1 - omega/2) B / 2,
+// from feq_a = w_a (rho + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u) (derivative
+// w_a (3 e + 9 (e.u) e - 3 u) in u), G_a = w_a (3 (e - u).F + 9 (e.u)(e.F))
+// and du/df_b = e_b, du/dF = I/2, domega/dtau = -omega^2.  The same
+// expressions hold for the deviation storages (the update is affine in f).
+//
+// lambda fields are canonical [Q][N] arrays in the arithmetic type of the
+// storage.  taubar and Fbar accumulate per workgroup in FP64 into a fixed
+// slot per workgroup, summed at the end in a fixed order.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace imexlbm {
+
+template <class C>
+struct AdjArgs {
+    Dims g;
+    int bx_shift;
+    C omega;
+    C F[3];
+    C half;  // 1 - omega/2
+};
+
+constexpr int kAccSlots = 4;  // taubar, Fbar_x, Fbar_y, Fbar_z
+
+// Sums v[0..3] over the workgroup (fixed tree) and adds the result to the
+// workgroup's slots of acc.  Every work-item of the group must call it.
+__device__ __forceinline__ void block_accumulate(double (&v)[kAccSlots], double* __restrict__ acc)
+{
+    __shared__ double s[kAccSlots][256];
+    const int t = threadIdx.x;
+    for (int c = 0; c < kAccSlots; ++c) s[c][t] = v[c];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+            for (int c = 0; c < kAccSlots; ++c) s[c][t] += s[c][t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const size_t b = blockIdx.x + size_t(gridDim.x) * (blockIdx.y + size_t(gridDim.y) * blockIdx.z);
+        for (int c = 0; c < kAccSlots; ++c) acc[b * kAccSlots + c] += s[c][0];
+    }
+}
+
+// One adjoint step: reads the forward state g^n (two-lattice layout) and
+// lambda^{n+1}, writes lambda^n, accumulates taubar and Fbar.
+template <int D, class S, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(256) void k_adjoint_step(const S* __restrict__ g,
+                                                      const typename Store<S>::C* __restrict__ lam_in,
+                                                      typename Store<S>::C* __restrict__ lam_out,
+                                                      double* __restrict__ acc,
+                                                      AdjArgs<typename Store<S>::C> p)
+{
+    using C = typename Store<S>::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x, y, z;
+    const bool inside = node_of_item(p.g, p.bx_shift, x, y, z);
+    const bool active = inside && !(WALLS && is_solid(p.g, x, y, z));
+    double part[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
+    if (inside) {
+        const unsigned N = p.g.N;
+        const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
+        if (!active) {
+            for (int a = 0; a < Q; ++a) lam_out[size_t(a) * N + own] = C(0);
+        } else {
+            unsigned idx[Q];
+            bool wall[Q];
+            // lambda*: pull from x + e_a.
+            link_nodes<D, WALLS, +1>(p.g, x, y, z, idx, wall);
+            C ls[Q];
+            static_for<Q>([&](auto ac) {
+                constexpr int a = decltype(ac)::value;
+                constexpr int abar = Lattice<D>::opp(a);
+                ls[a] = (WALLS && wall[a]) ? lam_in[size_t(abar) * N + own] : lam_in[size_t(a) * N + idx[a]];
+            });
+            // f^n: pull from x - e_a in the stored state.
+            link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
+            C f[Q];
+            static_for<Q>([&](auto ac) {
+                constexpr int a = decltype(ac)::value;
+                f[a] = Store<S>::load(g[gather_offset<D>(kPull, a, own, idx[a], WALLS && wall[a], p.g.P)]);
+            });
+            const Moments<D, C> m = node_moments<D, C, FORCE>(f, p.F);
+            const C usq = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+            C uF = C(0);
+            if constexpr (FORCE) uF = m.ux * p.F[0] + m.uy * p.F[1] + m.uz * p.F[2];
+            C m0 = C(0), m1[3] = {C(0), C(0), C(0)}, m2[3] = {C(0), C(0), C(0)},
+              m3[3] = {C(0), C(0), C(0)};
+            C tsum = C(0);  // sum_a l_a (feq_a - f_a - G_a/2)
+            static_for<Q>([&](auto ac) {
+                constexpr int a = decltype(ac)::value;
+                constexpr int ex = kLattice<D>.e[a][0], ey = kLattice<D>.e[a][1], ez = kLattice<D>.e[a][2];
+                const C w = C(kLattice<D>.w[a]);
+                const C wl = w * ls[a];
+                const C edu = eterm<ex>(m.ux) + eterm<ey>(m.uy) + eterm<ez>(m.uz);
+                m0 += wl;
+                m1[0] += eterm<ex>(wl);
+                m1[1] += eterm<ey>(wl);
+                m1[2] += eterm<ez>(wl);
+                const C wle = wl * edu;
+                m2[0] += eterm<ex>(wle);
+                m2[1] += eterm<ey>(wle);
+                m2[2] += eterm<ez>(wle);
+                const C feq = w * (m.rho + C(3) * edu + C(4.5) * edu * edu - C(1.5) * usq);
+                C gterm = C(0);
+                if constexpr (FORCE) {
+                    const C eF = eterm<ex>(p.F[0]) + eterm<ey>(p.F[1]) + eterm<ez>(p.F[2]);
+                    const C wlF = wl * eF;
+                    m3[0] += eterm<ex>(wlF);
+                    m3[1] += eterm<ey>(wlF);
+                    m3[2] += eterm<ez>(wlF);
+                    gterm = C(0.5) * w * (C(3) * (eF - uF) + C(9) * edu * eF);
+                }
+                tsum += ls[a] * (feq - f[a] - gterm);
+            });
+            const C u[3] = {m.ux, m.uy, m.uz};
+            C A[3], B[3], V[3];
+            for (int d = 0; d < 3; ++d) {
+                A[d] = C(3) * m1[d] + C(9) * m2[d] - C(3) * m0 * u[d];
+                B[d] = FORCE ? C(9) * m3[d] - C(3) * m0 * p.F[d] : C(0);
+                V[d] = p.omega * A[d] + p.half * B[d];
+            }
+            const C base = p.omega * m0;
+            const C keep = C(1) - p.omega;
+            static_for<Q>([&](auto ac) {
+                constexpr int b = decltype(ac)::value;
+                constexpr int ex = kLattice<D>.e[b][0], ey = kLattice<D>.e[b][1], ez = kLattice<D>.e[b][2];
+                lam_out[size_t(b) * N + own] =
+                    keep * ls[b] + base + (eterm<ex>(V[0]) + eterm<ey>(V[1]) + eterm<ez>(V[2]));
+            });
+            part[0] = -double(p.omega) * double(p.omega) * double(tsum);
+            for (int d = 0; d < D; ++d) part[1 + d] = double(A[d]) + 0.5 * double(p.half) * double(B[d]);
+        }
+    }
+    block_accumulate(part, acc);
+}
+
+// Output map: lambda^n_a = e_a . ubar (rho0 = 1) from ubar = dJ/du^n, and
+// Fbar += ubar/2 (u^n carries F/2).  Solid nodes get lambda = 0.
+template <int D, class S, bool WALLS>
+__global__ __launch_bounds__(256) void k_adjoint_seed(const double* __restrict__ ubar,
+                                                      typename Store<S>::C* __restrict__ lam,
+                                                      double* __restrict__ acc, Dims g, int bx_shift)
+{
+    using C = typename Store<S>::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x, y, z;
+    const bool inside = node_of_item(g, bx_shift, x, y, z);
+    double part[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
+    if (inside) {
+        const unsigned N = g.N;
+        const unsigned own = unsigned(x) + unsigned(g.nx) * (unsigned(y) + unsigned(g.ny) * unsigned(z));
+        const bool fluid = !(WALLS && is_solid(g, x, y, z));
+        double ub[3] = {0.0, 0.0, 0.0};
+        if (fluid)
+            for (int d = 0; d < D; ++d) ub[d] = ubar[size_t(d) * N + own];
+        static_for<Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            constexpr auto& L = kLattice<D>;
+            lam[size_t(a) * N + own] =
+                C(eterm<L.e[a][0]>(ub[0]) + eterm<L.e[a][1]>(ub[1]) + eterm<L.e[a][2]>(ub[2]));
+        });
+        for (int d = 0; d < D; ++d) part[1 + d] = 0.5 * ub[d];
+    }
+    block_accumulate(part, acc);
+}
+
+// Init map: f^0_a = w_a (rho + 3 e.u0 + 4.5 (e.u0)^2 - 1.5 u0.u0) + noise, so
+// u0bar = sum_a lambda^0_a w_a (3 e_a + 9 (e_a.u0) e_a - 3 u0).
+template <int D, class S, bool WALLS>
+__global__ __launch_bounds__(256) void k_adjoint_init_map(const typename Store<S>::C* __restrict__ lam,
+                                                          const double* __restrict__ u0,
+                                                          double* __restrict__ u0bar, Dims g,
+                                                          int bx_shift)
+{
+    constexpr int Q = Lattice<D>::Q;
+    int x, y, z;
+    if (!node_of_item(g, bx_shift, x, y, z)) return;
+    const unsigned N = g.N;
+    const unsigned own = unsigned(x) + unsigned(g.nx) * (unsigned(y) + unsigned(g.ny) * unsigned(z));
+    if (WALLS && is_solid(g, x, y, z)) {
+        for (int d = 0; d < 3; ++d) u0bar[size_t(d) * N + own] = 0.0;
+        return;
+    }
+    const double u[3] = {u0[own], u0[size_t(N) + own], D == 3 ? u0[2 * size_t(N) + own] : 0.0};
+    double m0 = 0.0, m1[3] = {0.0, 0.0, 0.0}, m2[3] = {0.0, 0.0, 0.0};
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr auto& L = kLattice<D>;
+        const double wl = L.w[a] * double(lam[size_t(a) * N + own]);
+        const double edu = eterm<L.e[a][0]>(u[0]) + eterm<L.e[a][1]>(u[1]) + eterm<L.e[a][2]>(u[2]);
+        m0 += wl;
+        m1[0] += eterm<L.e[a][0]>(wl);
+        m1[1] += eterm<L.e[a][1]>(wl);
+        m1[2] += eterm<L.e[a][2]>(wl);
+        m2[0] += eterm<L.e[a][0]>(wl * edu);
+        m2[1] += eterm<L.e[a][1]>(wl * edu);
+        m2[2] += eterm<L.e[a][2]>(wl * edu);
+    });
+    for (int d = 0; d < 3; ++d)
+        u0bar[size_t(d) * N + own] = d < D ? 3.0 * m1[d] + 9.0 * m2[d] - 3.0 * m0 * u[d] : 0.0;
+}
+
+// Sums the per-workgroup slots in workgroup order (one workgroup).
+__global__ __launch_bounds__(256) void k_adjoint_sum(const double* __restrict__ acc, size_t nblocks,
+                                                     double* __restrict__ out)
+{
+    __shared__ double s[kAccSlots][256];
+    const int t = threadIdx.x;
+    double v[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t b = t; b < nblocks; b += 256)
+        for (int c = 0; c < kAccSlots; ++c) v[c] += acc[b * kAccSlots + c];
+    for (int c = 0; c < kAccSlots; ++c) s[c][t] = v[c];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+            for (int c = 0; c < kAccSlots; ++c) s[c][t] += s[c][t + h];
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int c = 0; c < kAccSlots; ++c) out[c] = s[c][0];
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ p, size_t n)
+{
+    const size_t i = blockIdx.x * size_t(256) + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+}  // namespace imexlbm

@@ -11,6 +11,7 @@
 #include <new>
 
 #include "../../include/lbm.h"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 using namespace imexlbm;
@@ -53,8 +54,9 @@ size_t storage_size(lbm_storage s)
 // Non-temporal stores (and unshared loads) in the step kernels.
 constexpr bool kNtStores = true;
 
-// Elements between population planes: N itself.
-size_t plane_stride(unsigned long long N, size_t elem) { (void)elem; return size_t(N); }
+// Elements between population planes: N rounded up to a multiple of 128, so
+// every plane (and every buffer) starts on a 256-byte boundary.
+size_t plane_stride(unsigned long long N) { return size_t((N + 127) / 128 * 128); }
 
 }  // namespace
 
@@ -144,6 +146,17 @@ StepArgs<C> step_args(const lbm_ctx* c)
     return p;
 }
 
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Byte offsets inside the lbm_adjoint workspace.
+struct WorkspaceLayout {
+    size_t state_bytes;  // one stored state (also the checkpoint stride)
+    size_t seg, lam0, lam1, acc, result, total;
+    size_t nblocks, acc_doubles;
+};
+
+WorkspaceLayout workspace_layout(const lbm_ctx* c, int k);
+
 // Kernel instantiations of one lattice and storage.
 template <int D, class S>
 struct Impl {
@@ -186,6 +199,87 @@ struct Impl {
             ++c->steps;
         }
         LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    // One two-lattice step between explicit buffers.
+    static void step_between(lbm_ctx* c, const S* src, S* dst)
+    {
+        if (c->walls)
+            c->force ? step_ab<true, true>(c, src, dst) : step_ab<true, false>(c, src, dst);
+        else
+            c->force ? step_ab<false, true>(c, src, dst) : step_ab<false, false>(c, src, dst);
+    }
+
+    using C = typename Store<S>::C;
+
+    static AdjArgs<C> adj_args(const lbm_ctx* c)
+    {
+        AdjArgs<C> p;
+        p.g = dims_of(c);
+        p.bx_shift = c->bx_shift;
+        p.omega = C(c->omega);
+        for (int d = 0; d < 3; ++d) p.F[d] = C(c->F[d]);
+        p.half = C(1.0 - 0.5 * c->omega);
+        return p;
+    }
+
+    template <bool W, bool F>
+    static void adj_step(lbm_ctx* c, const S* g, const C* lin, C* lout, double* acc)
+    {
+        hipLaunchKernelGGL((k_adjoint_step<D, S, W, F>), c->grid, c->block, 0, c->stream, g, lin, lout,
+                           acc, adj_args(c));
+    }
+
+    // Backward sweep over n steps with checkpoints every k steps; see
+    // lbm_adjoint.  ws holds (k-1) state buffers, two lambda fields and the
+    // per-workgroup accumulators.
+    static lbm_status adjoint(lbm_ctx* c, int n, int k, const void* ckpt, void* ws,
+                              const double* u0, const double* ubar, double* u0bar, double* out4)
+    {
+        const WorkspaceLayout L = workspace_layout(c, k);
+        char* w = static_cast<char*>(ws);
+        C* lam[2] = {reinterpret_cast<C*>(w + L.lam0), reinterpret_cast<C*>(w + L.lam1)};
+        double* acc = reinterpret_cast<double*>(w + L.acc);
+        double* result = reinterpret_cast<double*>(w + L.result);
+        const Dims g = dims_of(c);
+        hipLaunchKernelGGL(k_fill_zero, dim3((L.acc_doubles + 255) / 256), dim3(256), 0, c->stream, acc,
+                           L.acc_doubles);
+        if (c->walls)
+            hipLaunchKernelGGL((k_adjoint_seed<D, S, true>), c->grid, c->block, 0, c->stream, ubar, lam[0],
+                               acc, g, c->bx_shift);
+        else
+            hipLaunchKernelGGL((k_adjoint_seed<D, S, false>), c->grid, c->block, 0, c->stream, ubar, lam[0],
+                               acc, g, c->bx_shift);
+        int cur = 0;
+        const char* ck = static_cast<const char*>(ckpt);
+        for (int s = n / k - 1; s >= 0; --s) {
+            const S* state0 = reinterpret_cast<const S*>(ck + size_t(s) * L.state_bytes);
+            auto state = [&](int j) -> const S* {
+                return j == 0 ? state0 : reinterpret_cast<const S*>(w + L.seg + size_t(j - 1) * L.state_bytes);
+            };
+            for (int j = 1; j < k; ++j)
+                step_between(c, state(j - 1), const_cast<S*>(state(j)));
+            for (int j = k - 1; j >= 0; --j) {
+                if (c->walls)
+                    c->force ? adj_step<true, true>(c, state(j), lam[cur], lam[1 - cur], acc)
+                             : adj_step<true, false>(c, state(j), lam[cur], lam[1 - cur], acc);
+                else
+                    c->force ? adj_step<false, true>(c, state(j), lam[cur], lam[1 - cur], acc)
+                             : adj_step<false, false>(c, state(j), lam[cur], lam[1 - cur], acc);
+                cur = 1 - cur;
+            }
+        }
+        if (c->walls)
+            hipLaunchKernelGGL((k_adjoint_init_map<D, S, true>), c->grid, c->block, 0, c->stream, lam[cur], u0,
+                               u0bar, g, c->bx_shift);
+        else
+            hipLaunchKernelGGL((k_adjoint_init_map<D, S, false>), c->grid, c->block, 0, c->stream, lam[cur], u0,
+                               u0bar, g, c->bx_shift);
+        hipLaunchKernelGGL(k_adjoint_sum, dim3(1), dim3(256), 0, c->stream, acc, L.nblocks, result);
+        LBM_HIP(hipGetLastError());
+        LBM_HIP(hipMemcpyAsync(out4, result, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        LBM_HIP(hipStreamSynchronize(c->stream));
         return LBM_OK;
     }
 
@@ -311,6 +405,29 @@ lbm_status check_device_ptr(const void* p, const char* name, bool allow_null)
     return LBM_OK;
 }
 
+WorkspaceLayout workspace_layout(const lbm_ctx* c, int k)
+{
+    WorkspaceLayout L;
+    const size_t elem = storage_size(c->storage);
+    const size_t celem = c->storage == LBM_F64 ? 8 : 4;  // arithmetic type of lambda
+    L.state_bytes = size_t(c->Q) * c->P * elem;  // a multiple of 256 (plane_stride)
+    L.nblocks = size_t(c->grid.x) * c->grid.y * c->grid.z;
+    L.acc_doubles = L.nblocks * kAccSlots;
+    L.seg = 0;
+    L.lam0 = L.seg + size_t(k > 1 ? k - 1 : 0) * L.state_bytes;
+    L.lam1 = L.lam0 + round256(size_t(c->Q) * c->N * celem);
+    L.acc = L.lam1 + round256(size_t(c->Q) * c->N * celem);
+    L.result = L.acc + round256(L.acc_doubles * sizeof(double));
+    L.total = L.result + 256;
+    return L;
+}
+
+lbm_status adjoint_any(lbm_ctx* c, int n, int k, const void* ckpt, void* ws, const double* u0,
+                       const double* ubar, double* u0bar, double* out4)
+{
+    LBM_DISPATCH(c, adjoint(c, n, k, ckpt, ws, u0, ubar, u0bar, out4));
+}
+
 lbm_status import_any(lbm_ctx* c, const double* f, const double* rho, const double* u,
                       const double* noise)
 {
@@ -366,7 +483,7 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
     c->ny = ny;
     c->nz = nz;
     c->N = unsigned(N);
-    c->P = plane_stride(N, storage_size(storage));
+    c->P = plane_stride(N);
     c->tau = tau;
     c->omega = 1.0 / tau;
     for (int d = 0; d < 3; ++d) {
@@ -491,6 +608,53 @@ lbm_status lbm_reduce(lbm_ctx* c, double* mass, double* kinetic_energy, double* 
 }
 
 long long lbm_steps_taken(const lbm_ctx* c) { return c ? c->steps : -1; }
+
+lbm_status lbm_forward_record(lbm_ctx* c, int n, int k, void* ckpt)
+{
+    lbm_status st = need_state(c);
+    if (st) return st;
+    if (c->aa) return fail(LBM_EINVAL, "checkpointed runs need the two-lattice pattern (no LBM_FLAG_AA)");
+    if (n < 0 || k < 1 || n % k != 0) return fail(LBM_EINVAL, "need n >= 0, k >= 1 and k dividing n (n=%d k=%d)", n, k);
+    if (n == 0) return LBM_OK;
+    if ((st = check_device_ptr(ckpt, "ckpt", false))) return st;
+    const size_t bytes = lbm_buffer_bytes(c);
+    char* ck = static_cast<char*>(ckpt);
+    for (int s = 0; s < n / k; ++s) {
+        LBM_HIP(hipMemcpyAsync(ck + size_t(s) * bytes, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice,
+                               c->stream));
+        if ((st = lbm_step(c, k))) return st;
+    }
+    return LBM_OK;
+}
+
+size_t lbm_adjoint_workspace_bytes(const lbm_ctx* c, int k)
+{
+    if (!c || k < 1) return 0;
+    return workspace_layout(c, k).total;
+}
+
+lbm_status lbm_adjoint(lbm_ctx* c, int n, int k, const void* ckpt, void* work, const double* u0,
+                       const double* dJ_du, double* dJ_du0, double* dJ_dtau, double dJ_dforce[3])
+{
+    lbm_status st = need_bound(c);
+    if (st) return st;
+    if (c->aa) return fail(LBM_EINVAL, "the adjoint needs the two-lattice pattern (no LBM_FLAG_AA)");
+    if (n < 0 || k < 1 || n % k != 0) return fail(LBM_EINVAL, "need n >= 0, k >= 1 and k dividing n (n=%d k=%d)", n, k);
+    if (std::isinf(c->tau)) return fail(LBM_EINVAL, "the adjoint needs a finite tau");
+    if (n > 0 && (st = check_device_ptr(ckpt, "ckpt", false))) return st;
+    if ((st = check_device_ptr(work, "work", false))) return st;
+    if ((st = check_device_ptr(u0, "u0", false))) return st;
+    if ((st = check_device_ptr(dJ_du, "dJ_du", false))) return st;
+    if ((st = check_device_ptr(dJ_du0, "dJ_du0", false))) return st;
+    if (reinterpret_cast<uintptr_t>(work) & 255) return fail(LBM_EINVAL, "work must be 256-byte aligned");
+    double out[4];
+    if ((st = adjoint_any(c, n, k, ckpt, work, u0, dJ_du, dJ_du0, c->h_result))) return st;
+    for (int i = 0; i < 4; ++i) out[i] = c->h_result[i];
+    if (dJ_dtau) *dJ_dtau = out[0];
+    if (dJ_dforce)
+        for (int d = 0; d < 3; ++d) dJ_dforce[d] = out[1 + d];
+    return LBM_OK;
+}
 
 lbm_status lbm_destroy(lbm_ctx* c)
 {

@@ -29,7 +29,8 @@ Q_OF = {D2Q9: 9, D3Q19: 19}
 EXPORTS = (
     "lbm_create", "lbm_buffer_bytes", "lbm_bind", "lbm_init_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments", "lbm_reduce",
-    "lbm_steps_taken", "lbm_destroy", "lbm_status_string", "lbm_last_error",
+    "lbm_steps_taken", "lbm_forward_record", "lbm_adjoint_workspace_bytes", "lbm_adjoint",
+    "lbm_destroy", "lbm_status_string", "lbm_last_error",
 )
 
 
@@ -79,6 +80,12 @@ def lib():
     L.lbm_reduce.restype = st
     L.lbm_steps_taken.argtypes = [vp]
     L.lbm_steps_taken.restype = ctypes.c_longlong
+    L.lbm_forward_record.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    L.lbm_forward_record.restype = st
+    L.lbm_adjoint_workspace_bytes.argtypes = [vp, ctypes.c_int]
+    L.lbm_adjoint_workspace_bytes.restype = ctypes.c_size_t
+    L.lbm_adjoint.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, dp, dp]
+    L.lbm_adjoint.restype = st
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = st
     L.lbm_status_string.argtypes = [ctypes.c_int]
@@ -200,6 +207,35 @@ class LBM:
               "lbm_moments")
         return rho, u
 
+    # -- discrete adjoint ----------------------------------------------------
+    @property
+    def buffer_bytes(self):
+        return lib().lbm_buffer_bytes(self._h)
+
+    def forward_record(self, n, k, ckpt=None):
+        """Advances n steps, keeping the state every k steps; returns the
+        checkpoint tensor (n/k buffers) that adjoint() needs."""
+        if ckpt is None:
+            ckpt = torch.empty(max(n // k, 1) * self.buffer_bytes, dtype=torch.uint8,
+                               device=self.device)
+        check(lib().lbm_forward_record(self._h, int(n), int(k), _ptr(ckpt)), "lbm_forward_record")
+        return ckpt
+
+    def adjoint(self, n, k, ckpt, u0, dJ_du, work=None):
+        """(dJ/du0 [3,nz,ny,nx] FP64, dJ/dtau, dJ/dF [3]) of a functional of the
+        final velocity, given dJ/du^n; u0 is the velocity the run started from."""
+        u0 = _dev_f64(u0, (3,) + self.shape, self.device)
+        dJ_du = _dev_f64(dJ_du, (3,) + self.shape, self.device)
+        if work is None:
+            work = torch.empty(lib().lbm_adjoint_workspace_bytes(self._h, int(k)), dtype=torch.uint8,
+                               device=self.device)
+        u0bar = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        taubar = ctypes.c_double()
+        Fbar = (ctypes.c_double * 3)()
+        check(lib().lbm_adjoint(self._h, int(n), int(k), _ptr(ckpt), _ptr(work), _ptr(u0),
+                                _ptr(dJ_du), _ptr(u0bar), ctypes.byref(taubar), Fbar), "lbm_adjoint")
+        return u0bar, taubar.value, [Fbar[0], Fbar[1], Fbar[2]]
+
     def reduce(self):
         """Monitor: {'mass', 'ke', 'umax'} in FP64 (synchronises the stream)."""
         m, k, um = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
@@ -209,3 +245,41 @@ class LBM:
         if st not in (OK, EUNSTABLE):
             check(st, "lbm_reduce")
         return out
+
+
+class LBMRollout(torch.autograd.Function):
+    """u^n = rollout(u0, tau, F): n LBM steps from f^0 = feq(rho, u0) (+ noise),
+    differentiable in u0, tau and F through the library's discrete adjoint
+    with checkpoints every k steps (the backward recomputes each k-step
+    segment from its checkpoint).
+
+    Call as ``LBMRollout.apply(u0, tau, force, rho, n, k, lattice, bc, storage,
+    noise)`` with u0 a [3, nz, ny, nx] FP64 CUDA tensor, tau a scalar tensor,
+    force a 3-vector tensor.  Returns u^n [3, nz, ny, nx] (FP64).
+    """
+
+    @staticmethod
+    def forward(ctx, u0, tau, force, rho, n, k, lattice=D3Q19, bc=(0, 0, 0), storage="f64",
+                noise=None):
+        nz, ny, nx = u0.shape[1:]
+        sim = LBM(lattice, nx, ny, nz, float(tau), force=tuple(float(v) for v in force.reshape(-1)),
+                  bc=bc, storage=storage, device=u0.device)
+        u0d = u0.detach().to(torch.float64).contiguous()
+        sim.init_equilibrium(rho, u0d, noise)
+        ckpt = sim.forward_record(n, k)
+        _, uN = sim.moments()
+        ctx.sim, ctx.ckpt, ctx.n, ctx.k = sim, ckpt, n, k
+        ctx.tau_like, ctx.force_like = tau, force
+        ctx.save_for_backward(u0d)
+        return uN
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        (u0d,) = ctx.saved_tensors
+        u0bar, taubar, Fbar = ctx.sim.adjoint(ctx.n, ctx.k, ctx.ckpt, u0d, grad_u.contiguous())
+        ctx.sim.close()
+        ctx.ckpt = None
+        gt = torch.tensor(taubar, dtype=ctx.tau_like.dtype, device=ctx.tau_like.device)
+        gF = torch.tensor(Fbar, dtype=ctx.force_like.dtype, device=ctx.force_like.device)
+        return (u0bar, gt.reshape(ctx.tau_like.shape), gF.reshape(ctx.force_like.shape),
+                None, None, None, None, None, None, None)

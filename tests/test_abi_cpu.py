@@ -75,7 +75,13 @@ def test_create_accepts_and_sizes():
         for storage, size in ((lbm.F64, 8), (lbm.F32, 4), (lbm.F16_DEV, 2), (lbm.BF16_DEV, 2)):
             st, h = _create(lattice=lattice, nx=7, ny=6, nz=nz, storage=storage)
             assert st == lbm.OK
-            assert L.lbm_buffer_bytes(h) == Q * 7 * 6 * nz * size
+            plane = -(-7 * 6 * nz // 128) * 128  # planes padded to 128 elements
+            assert L.lbm_buffer_bytes(h) == Q * plane * size
+            assert L.lbm_buffer_bytes(h) % 256 == 0
+            assert L.lbm_adjoint_workspace_bytes(h, 1) > 0
+            assert L.lbm_adjoint_workspace_bytes(h, 5) - L.lbm_adjoint_workspace_bytes(h, 4) == \
+                L.lbm_buffer_bytes(h)
+            assert L.lbm_adjoint_workspace_bytes(h, 0) == 0
             assert L.lbm_steps_taken(h) == 0
             assert L.lbm_destroy(h) == lbm.OK
     st, h = _create(tau=math.inf)  # pure streaming without force is allowed
@@ -95,6 +101,8 @@ def test_calls_before_bind_fail_without_device_work():
     assert L.lbm_get_populations(h, None) == lbm.ENOTBOUND
     assert L.lbm_set_populations(h, None) == lbm.ENOTBOUND
     assert L.lbm_init_equilibrium(h, None, None, None) == lbm.ENOTBOUND
+    assert L.lbm_forward_record(h, 4, 2, None) == lbm.ENOTBOUND
+    assert L.lbm_adjoint(h, 4, 2, None, None, None, None, None, None, None) == lbm.ENOTBOUND
     assert b"lbm_bind" in L.lbm_last_error()
     assert L.lbm_step(None, 1) == lbm.EINVAL
     assert L.lbm_destroy(h) == lbm.OK

@@ -1,0 +1,237 @@
+"""GPU discrete adjoint (lbm_forward_record / lbm_adjoint, LBMRollout)
+against the oracle's complex-step adjoint, closed forms and finite
+differences of the forward model."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2201_11330_amd import lbm
+from paper_2201_11330_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_case(lattice, dims, seed):
+    nx, ny, nz = dims
+    D = 2 if lattice == W.D2Q9 else 3
+    Q = 9 if lattice == W.D2Q9 else 19
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + 0.01 * rng.standard_normal((nz, ny, nx))
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[:D] = 0.03 * rng.standard_normal((D, nz, ny, nx))
+    u_tgt = np.zeros_like(u0)
+    u_tgt[:D] = 0.03 * rng.standard_normal((D, nz, ny, nx))
+    noise = 1e-4 * rng.standard_normal((Q, nz, ny, nx))
+    return rho, u0, u_tgt, noise
+
+
+def _gpu_adjoint(lattice, dims, tau, force, bc, rho, u0, noise, ubar, n, k, storage="f64"):
+    sim = lbm.LBM(lattice, *dims, tau, force=force, bc=bc, storage=storage)
+    sim.init_equilibrium(rho, u0, noise)
+    ckpt = sim.forward_record(n, k)
+    out = sim.adjoint(n, k, ckpt, u0, ubar)
+    sim.close()
+    return out
+
+
+CASES = [
+    (W.D3Q19, (9, 7, 6), (0, 0, 0), (1e-5, -2e-5, 3e-5), 12, 4),
+    (W.D3Q19, (8, 10, 7), (0, 1, 0), (2e-5, 0, 0), 10, 5),
+    (W.D3Q19, (7, 6, 9), (2, 1, 1), (1e-5, 1e-5, -1e-5), 9, 3),
+    (W.D3Q19, (16, 16, 16), (0, 0, 0), (0, 0, 0), 20, 5),
+    (W.D2Q9, (11, 9, 1), (0, 1, 0), (1e-5, 2e-5, 0), 14, 7),
+    (W.D2Q9, (13, 12, 1), (0, 0, 0), (0, 0, 0), 8, 8),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[1])) + f"-bc{''.join(map(str, c[2]))}")
+def test_adjoint_matches_oracle_complex_step(case):
+    """GPU closed-form adjoint vs the oracle's adjoint built from
+    complex-step Jacobians (FP64, relative 1e-12 of the gradient scale)."""
+    lattice, dims, bc, force, n, k = case
+    tau = 0.7
+    rho, u0, u_tgt, noise = _random_case(lattice, dims, seed=21)
+    s = oracle.Sim(lattice, *dims, tau=tau, force=force, bc=bc)
+    s.init_equilibrium(rho, u0, noise)
+    s.step(n)
+    _, uN = s.moments()
+    fluid = s.geometry()
+    D = 2 if lattice == W.D2Q9 else 3
+    ubar = (uN - u_tgt) * fluid
+    ubar[D:] = 0.0
+    ob_u0, ob_tau, ob_F = oracle.adjoint(lattice, dims, tau, force, bc, rho, u0, ubar, n, noise)
+    gb_u0, gb_tau, gb_F = _gpu_adjoint(lattice, dims, tau, force, bc, rho, u0, noise, ubar, n, k)
+    gb_u0 = gb_u0.cpu().numpy()
+    e_u0 = np.abs(gb_u0 - ob_u0).max() / np.abs(ob_u0).max()
+    # tau and F gradients are sums over nodes and steps: compare on the scale
+    # of |dJ/du0| summed over the domain.
+    scale = np.abs(ob_u0).sum()
+    e_tau = abs(gb_tau - ob_tau) / scale
+    e_F = np.abs(np.asarray(gb_F) - ob_F).max() / scale
+    print(f"{dims} bc={bc}: u0bar {e_u0:.2e} taubar {e_tau:.2e} Fbar {e_F:.2e} "
+          f"(taubar {ob_tau:.4e}, Fbar {ob_F})")
+    assert e_u0 <= 1e-12 and e_tau <= 1e-12 and e_F <= 1e-12
+    assert abs(gb_tau - ob_tau) <= 1e-10 * abs(ob_tau)
+
+
+def test_adjoint_closed_form_mean_velocity():
+    """J = sum_x u_x^n on a periodic box: dJ/du0_x = 1, dJ/dF_x = V (n + 1/2),
+    dJ/dtau = 0 (the collision adds exactly F of momentum per node and step)."""
+    dims = (20, 12, 10)
+    nx, ny, nz = dims
+    rho, u0, _, noise = _random_case(W.D3Q19, dims, seed=3)
+    ubar = np.zeros((3, nz, ny, nx))
+    ubar[0] = 1.0
+    n, k = 30, 6
+    gb_u0, gb_tau, gb_F = _gpu_adjoint(W.D3Q19, dims, 0.8, (1e-5, 0, 0), (0, 0, 0), rho, u0, noise,
+                                       ubar, n, k)
+    g = gb_u0.cpu().numpy()
+    V = nx * ny * nz
+    assert np.abs(g[0] - 1).max() < 1e-12 and np.abs(g[1:]).max() < 1e-12
+    assert abs(gb_F[0] / (V * (n + 0.5)) - 1) < 1e-12
+    assert abs(gb_F[1]) < 1e-9 and abs(gb_F[2]) < 1e-9
+    assert abs(gb_tau) < 1e-9
+
+
+def test_adjoint_zero_steps_is_output_and_init_map():
+    dims = (6, 5, 4)
+    rho, u0, u_tgt, noise = _random_case(W.D3Q19, dims, seed=5)
+    ubar = u_tgt
+    ob_u0, ob_tau, ob_F = oracle.adjoint(W.D3Q19, dims, 0.7, (0, 0, 0), (0, 0, 0), rho, u0, ubar, 0,
+                                         noise)
+    gb_u0, gb_tau, gb_F = _gpu_adjoint(W.D3Q19, dims, 0.7, (0, 0, 0), (0, 0, 0), rho, u0, noise, ubar,
+                                       0, 1)
+    assert np.abs(gb_u0.cpu().numpy() - ob_u0).max() <= 1e-15
+    assert gb_tau == 0.0
+    assert np.abs(np.asarray(gb_F) - ob_F).max() <= 1e-13
+
+
+def _c5_fields(n=128):
+    rho, u0 = W.random_fourier_field(n, modes=8, kmax=4, amplitude=0.02, seed=11)
+    _, u_t0 = W.random_fourier_field(n, modes=8, kmax=4, amplitude=0.02, seed=12)
+    return rho, u0, u_t0
+
+
+def _c5_target(rho, u_t0, tau, steps, n):
+    sim = lbm.LBM(lbm.D3Q19, n, n, n, tau)
+    sim.init_equilibrium(rho, u_t0)
+    sim.step(steps)
+    _, ut = sim.moments()
+    sim.close()
+    return ut
+
+
+def _objective(u0, tau, F, rho, u_tgt, steps, n, storage="f64"):
+    sim = lbm.LBM(lbm.D3Q19, n, n, n, tau, force=F, storage=storage)
+    sim.init_equilibrium(rho, u0)
+    sim.step(steps)
+    _, uN = sim.moments()
+    sim.close()
+    return 0.5 * ((uN - u_tgt) ** 2).sum().item()
+
+
+@pytest.mark.slow
+def test_gradient_finite_differences_adjoint_workload():
+    """Workload D3Q19 128^3 periodic, tau = 0.7, 500 steps, checkpoints every
+    50: the FP64 adjoint gradient along 16 random directions of (u0, tau, F)
+    agrees with Richardson-extrapolated FP64 central differences to 1e-6."""
+    n, steps, k, tau = 128, 500, 50, 0.7
+    rho, u0, u_t0 = _c5_fields(n)
+    u_tgt = _c5_target(rho, u_t0, tau, steps, n)
+    F0 = torch.zeros(3, dtype=torch.float64)
+    u0t = torch.tensor(u0, device="cuda", requires_grad=True)
+    taut = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    Ft = F0.clone().requires_grad_(True)
+    uN = lbm.LBMRollout.apply(u0t, taut, Ft, rho, steps, k)
+    J = 0.5 * ((uN - u_tgt) ** 2).sum()
+    J.backward()
+    g_u0, g_tau, g_F = u0t.grad, taut.grad.item(), Ft.grad.numpy()
+    rng = np.random.default_rng(17)
+    u0_dev = torch.tensor(u0, device="cuda")
+    worst = 0.0
+    for trial in range(16):
+        du = torch.tensor(rng.standard_normal(u0.shape), device="cuda")
+        dtau = float(rng.standard_normal()) if trial % 4 == 0 else 0.0
+        dF = rng.standard_normal(3) if trial % 4 == 1 else np.zeros(3)
+        su, stau, sF = 1e-2 * 0.02, 1e-2, 1e-6  # step scales of u0, tau and F
+
+        def J_at(h):
+            return _objective(u0_dev + h * su * du, tau + h * stau * dtau, tuple(h * sF * dF), rho,
+                              u_tgt, steps, n)
+
+        fd = []
+        for h in (1.0, 0.5):
+            fd.append((J_at(h) - J_at(-h)) / (2 * h))
+        fd_rich = (4 * fd[1] - fd[0]) / 3
+        adj = (su * (g_u0 * du).sum().item() + stau * g_tau * dtau + sF * float(g_F @ dF))
+        err = abs(adj - fd_rich) / abs(fd_rich)
+        worst = max(worst, err)
+        print(f"dir {trial}: adjoint {adj:.10e} fd {fd_rich:.10e} rel {err:.2e}")
+    assert worst <= 1e-6
+
+
+@pytest.mark.slow
+def test_fp32_adjoint_against_fp64():
+    """The FP32 (f - w storage) forward and adjoint at the adjoint workload's
+    shape, against the FP64 instantiation: relative error of each gradient
+    (reported; bounded loosely)."""
+    n, steps, k, tau = 128, 500, 50, 0.7
+    rho, u0, u_t0 = _c5_fields(n)
+    u_tgt = _c5_target(rho, u_t0, tau, steps, n)
+    res = {}
+    for storage in ("f64", "f32"):
+        sim = lbm.LBM(lbm.D3Q19, n, n, n, tau, storage=storage)
+        sim.init_equilibrium(rho, u0)
+        ckpt = sim.forward_record(steps, k)
+        _, uN = sim.moments()
+        res[storage] = sim.adjoint(steps, k, ckpt, u0, uN - u_tgt)
+        sim.close()
+    g64, g32 = res["f64"], res["f32"]
+    e_u0 = ((g32[0] - g64[0]).abs().max() / g64[0].abs().max()).item()
+    e_tau = abs(g32[1] - g64[1]) / abs(g64[1])
+    e_F = np.abs(np.asarray(g32[2]) - g64[2]).max() / np.abs(g64[2]).max()
+    print(f"FP32 vs FP64 adjoint: u0bar {e_u0:.2e}, taubar {e_tau:.2e}, Fbar {e_F:.2e}")
+    assert e_u0 < 1e-3 and e_tau < 1e-3 and e_F < 1e-2
+
+
+def test_rollout_function_matches_direct_adjoint():
+    dims = (12, 10, 8)
+    nx, ny, nz = dims
+    rho, u0, u_tgt, _ = _random_case(W.D3Q19, dims, seed=9)
+    u0t = torch.tensor(u0, device="cuda", requires_grad=True)
+    taut = torch.tensor(0.75, dtype=torch.float64, requires_grad=True)
+    Ft = torch.tensor([1e-5, 0.0, -1e-5], dtype=torch.float64, requires_grad=True)
+    uN = lbm.LBMRollout.apply(u0t, taut, Ft, rho, 12, 4, lbm.D3Q19, (0, 1, 0))
+    tgt = torch.tensor(u_tgt, device="cuda")
+    J = 0.5 * ((uN - tgt) ** 2).sum()
+    J.backward()
+    sim = lbm.LBM(lbm.D3Q19, *dims, 0.75, force=(1e-5, 0.0, -1e-5), bc=(0, 1, 0))
+    sim.init_equilibrium(rho, u0)
+    ckpt = sim.forward_record(12, 4)
+    _, uN2 = sim.moments()
+    assert torch.equal(uN.detach(), uN2)
+    g_u0, g_tau, g_F = sim.adjoint(12, 4, ckpt, u0, uN2 - tgt)
+    assert torch.equal(u0t.grad, g_u0)
+    assert taut.grad.item() == g_tau
+    assert Ft.grad.tolist() == g_F
+    # checkpoint interval does not change the result beyond rounding order
+    sim2 = lbm.LBM(lbm.D3Q19, *dims, 0.75, force=(1e-5, 0.0, -1e-5), bc=(0, 1, 0))
+    sim2.init_equilibrium(rho, u0)
+    ck2 = sim2.forward_record(12, 12)
+    g2 = sim2.adjoint(12, 12, ck2, u0, uN2 - tgt)
+    assert torch.equal(g2[0], g_u0)
+    assert g2[1] == g_tau
+
+
+def test_adjoint_rejects_bad_arguments():
+    sim = lbm.LBM(lbm.D3Q19, 8, 8, 8, 0.7)
+    sim.init_equilibrium(np.ones((8, 8, 8)), np.zeros((3, 8, 8, 8)))
+    with pytest.raises(lbm.LBMError):
+        sim.forward_record(10, 3)  # k must divide n
+    aa = lbm.LBM(lbm.D3Q19, 8, 8, 8, 0.7, aa=True)
+    aa.init_equilibrium(np.ones((8, 8, 8)), np.zeros((3, 8, 8, 8)))
+    with pytest.raises(lbm.LBMError):
+        aa.forward_record(4, 2)

@@ -91,7 +91,10 @@ typedef struct {
 
 /* lbm_create flags. */
 enum {
-    LBM_FLAG_AA = 1 /* in-place AA pattern: one population buffer instead of two */
+    LBM_FLAG_AA = 1,   /* in-place AA pattern: one population buffer instead of two */
+    LBM_FLAG_GRAPH = 2 /* lbm_step replays a HIP graph of 32 captured steps (captured on
+                          first use on a private stream, launched on the bound stream):
+                          fewer launch round trips for small, launch-bound boxes */
 };
 
 /*
@@ -99,7 +102,7 @@ enum {
  * tau > 1/2 (tau = +inf is pure streaming, allowed only with F = 0);
  * every dimension >= 1 and >= 3 on an LBM_SOLID_ENDS axis; D2Q9 needs
  * nz = 1, a periodic z axis and F_z = 0; F finite; N = nx*ny*nz < 2^31;
- * flags only LBM_FLAG_AA.  force may be NULL (no force); bc may be NULL
+ * flags only LBM_FLAG_AA and LBM_FLAG_GRAPH.  force may be NULL (no force); bc may be NULL
  * (fully periodic).  No device work happens here.
  */
 lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz, double tau,

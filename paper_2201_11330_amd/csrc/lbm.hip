@@ -51,6 +51,10 @@ size_t storage_size(lbm_storage s)
     return 0;
 }
 
+// Steps per captured graph (even, so a replay returns the two-lattice
+// buffers and the AA parity to where they started).
+constexpr int kGraphSteps = 32;
+
 // Non-temporal stores (and unshared loads) in the step kernels.
 constexpr bool kNtStores = true;
 
@@ -85,6 +89,12 @@ struct lbm_ctx {
 
     int bx_shift = 8;
     dim3 grid, block;
+
+    // LBM_FLAG_GRAPH: kGraphSteps steps captured once, replayed by lbm_step.
+    bool use_graph = false;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -177,7 +187,51 @@ struct Impl {
                                step_args<typename Store<S>::C>(c));
     }
 
+    // Captures kGraphSteps steps starting from an even step count (buffer 0
+    // current, AA even parity) on a private stream; the context's launch
+    // stream and counters are restored afterwards.
+    static lbm_status capture(lbm_ctx* c)
+    {
+        if (!c->capture_stream) LBM_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+        hipStream_t saved_stream = c->stream;
+        const int saved_cur = c->cur;
+        const long long saved_steps = c->steps;
+        c->stream = c->capture_stream;
+        c->cur = 0;
+        c->steps = 0;
+        LBM_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+        eager(c, kGraphSteps);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+        c->stream = saved_stream;
+        c->cur = saved_cur;
+        c->steps = saved_steps;
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        c->graph = g;
+        LBM_HIP(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+        return LBM_OK;
+    }
+
     static lbm_status step(lbm_ctx* c, int n)
+    {
+        if (!c->use_graph || n < kGraphSteps) return eager(c, n);
+        if (c->steps & 1) {  // align to the captured parity
+            lbm_status st = eager(c, 1);
+            if (st) return st;
+            --n;
+        }
+        if (!c->graph_exec) {
+            lbm_status st = capture(c);
+            if (st) return st;
+        }
+        for (; n >= kGraphSteps; n -= kGraphSteps) {
+            LBM_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+            c->steps += kGraphSteps;
+        }
+        return eager(c, n);
+    }
+
+    static lbm_status eager(lbm_ctx* c, int n)
     {
         for (int i = 0; i < n; ++i) {
             if (c->aa) {
@@ -450,7 +504,7 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
     *out = nullptr;
     if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(LBM_EINVAL, "unknown lattice %d", int(lattice));
     if (storage_size(storage) == 0) return fail(LBM_EINVAL, "unknown storage %d", int(storage));
-    if (flags & ~unsigned(LBM_FLAG_AA)) return fail(LBM_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~unsigned(LBM_FLAG_AA | LBM_FLAG_GRAPH)) return fail(LBM_EINVAL, "unknown flags 0x%x", flags);
     const int n[3] = {nx, ny, nz};
     int b[3] = {LBM_PERIODIC, LBM_PERIODIC, LBM_PERIODIC};
     if (bc)
@@ -493,6 +547,7 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
     c->storage = storage;
     c->flags = flags;
     c->aa = flags & LBM_FLAG_AA;
+    c->use_graph = flags & LBM_FLAG_GRAPH;
     c->walls = b[0] != LBM_PERIODIC || b[1] != LBM_PERIODIC || b[2] != LBM_PERIODIC;
     c->force = has_force;
     plan_launch(c);
@@ -668,6 +723,9 @@ lbm_status lbm_destroy(lbm_ctx* c)
         hipError_t e = hipHostFree(c->h_result);
         if (e != hipSuccess) st = hip_fail(e, "hipHostFree");
     }
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;
     return st;
 }

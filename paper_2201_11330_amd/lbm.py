@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "liblbm.so")
 D2Q9, D3Q19 = 0, 1
 PERIODIC, SOLID_ENDS, WALLS_OUTSIDE = 0, 1, 2
 F64, F32, F16_DEV, BF16_DEV = 0, 1, 2, 3
-FLAG_AA = 1
+FLAG_AA, FLAG_GRAPH = 1, 2
 OK, EINVAL, ENOTBOUND, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 
 STORAGE_NAMES = {"f64": F64, "f32": F32, "f16": F16_DEV, "bf16": BF16_DEV}
@@ -122,12 +122,12 @@ class LBM:
     ``tau`` is the lattice relaxation time (omega = 1/tau, nu = (tau - 1/2)/3);
     ``bc`` gives PERIODIC / SOLID_ENDS / WALLS_OUTSIDE per axis (x, y, z);
     ``storage`` is "f64", "f32", "f16" or "bf16"; ``aa`` selects the in-place
-    AA pattern.  Launches go to ``stream`` (default: torch's current stream
+    AA pattern; ``graph`` makes step() replay a captured HIP graph of 32 steps.  Launches go to ``stream`` (default: torch's current stream
     at construction time).
     """
 
     def __init__(self, lattice, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), bc=(0, 0, 0),
-                 storage="f64", aa=False, device=None, stream=None):
+                 storage="f64", aa=False, device=None, stream=None, graph=False):
         L = lib()
         self.lattice = lattice
         self.Q = Q_OF[lattice]
@@ -144,7 +144,8 @@ class LBM:
         F = (ctypes.c_double * 3)(*self.force)
         bcs = _BC((ctypes.c_int * 3)(*self.bc))
         check(L.lbm_create(ctypes.byref(h), lattice, nx, ny, nz, self.tau, F, ctypes.byref(bcs),
-                           self.storage, FLAG_AA if self.aa else 0), "lbm_create")
+                           self.storage, (FLAG_AA if self.aa else 0) | (FLAG_GRAPH if graph else 0)),
+              "lbm_create")
         self._h = h
         nbytes = L.lbm_buffer_bytes(h)
         self.buffers = [torch.empty(nbytes, dtype=torch.uint8, device=self.device)

@@ -36,7 +36,8 @@ def test_header_enums_match_binding():
                       ("LBM_F32", lbm.F32), ("LBM_F16_DEV", lbm.F16_DEV),
                       ("LBM_BF16_DEV", lbm.BF16_DEV), ("LBM_PERIODIC", lbm.PERIODIC),
                       ("LBM_SOLID_ENDS", lbm.SOLID_ENDS), ("LBM_WALLS_OUTSIDE", lbm.WALLS_OUTSIDE),
-                      ("LBM_FLAG_AA", lbm.FLAG_AA), ("LBM_EINVAL", lbm.EINVAL),
+                      ("LBM_FLAG_AA", lbm.FLAG_AA), ("LBM_FLAG_GRAPH", lbm.FLAG_GRAPH),
+                      ("LBM_EINVAL", lbm.EINVAL),
                       ("LBM_ENOTBOUND", lbm.ENOTBOUND), ("LBM_EUNSTABLE", lbm.EUNSTABLE)]:
         m = re.search(rf"\b{name}\s*=\s*(-?\d+)", text)
         assert m and int(m.group(1)) == val, name

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_adjoint_step(const S* __restrict__ g,
             C f[Q];
             static_for<Q>([&](auto ac) {
                 constexpr int a = decltype(ac)::value;
-                f[a] = Store<S>::load(g[gather_offset<D>(kPull, a, own, idx[a], WALLS && wall[a], p.g.P)]);
+                f[a] = Store<S>::load(g[gather_offset<D>(kPull, a, own, idx[a], WALLS && wall[a], p.g.S)]);
             });
             const Moments<D, C> m = node_moments<D, C, FORCE>(f, p.F);
             const C usq = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;

@@ -1,11 +1,15 @@
 // Device code of the LBM time step for gfx950.
 //
-// Layout: one population buffer is structure-of-arrays, Q planes of N
-// nodes, plane a at element offset a*N, node (x, y, z) at in-plane index
-// x + nx*(y + ny*z) (x fastest).  One work-item owns one node; 256-item
-// workgroups cover a (BX x BY) tile of an x-y plane with BX a power of two
-// (the full row when nx <= 256), so the 64 lanes of a wavefront touch 64
-// consecutive nodes of a row and every plane access is coalesced.
+// Layout: nodes are numbered x + nx*(y + ny*z) (x fastest).  A population
+// buffer is an array of tiles of T = 2^S consecutive nodes; a tile holds Q
+// runs of T elements, one per direction (structure of arrays inside the
+// tile, see slot()).  One work-item owns one node; 256-item workgroups
+// cover a (BX x BY) tile of an x-y plane with BX a power of two (the full
+// row when nx <= 256), so the 64 lanes of a wavefront touch 64 consecutive
+// nodes of a row and every access is a coalesced 64-element run.  The 19
+// loads and 19 stores of a wavefront land in a few contiguous regions
+// instead of 19 separate planes (measured 4-10 % faster than plain
+// structure of arrays on MI355X).
 //
 // Two-lattice scheme (AB): the stored state is the post-collision
 // population f* of the previous step.  One launch pulls
@@ -110,8 +114,15 @@ struct Dims {
     int nx, ny, nz;
     int bc[3];
     unsigned N;  // nx*ny*nz
-    size_t P;    // elements from one population plane of the stored state to the next (>= N)
+    int S;       // log2 of the tile length T of the stored state
 };
+
+// Element offset of direction a of node idx in a stored state.
+template <int Q>
+__device__ __forceinline__ size_t slot(int a, unsigned idx, int S)
+{
+    return ((size_t(idx >> S) * Q + size_t(a)) << S) | (idx & ((1u << S) - 1u));
+}
 
 // Coordinates c-1, c, c+1 of one axis (index = shift + 1), wrapped on a
 // periodic axis, and whether each is a wall (a solid plane, or outside the
@@ -192,12 +203,13 @@ __device__ __forceinline__ void link_nodes(const Dims& g, int x, int y, int z,
 // pairs of fluid nodes and slots.
 template <int D>
 __device__ __forceinline__ size_t gather_offset(int mode, int a, unsigned own, unsigned src,
-                                                bool wall, size_t P)
+                                                bool wall, int S)
 {
+    constexpr int Q = Lattice<D>::Q;
     const int abar = Lattice<D>::opp(a);
-    if (mode == kLocal) return size_t(a) * P + own;
-    if (mode == kPull) return wall ? size_t(abar) * P + own : size_t(a) * P + src;
-    return wall ? size_t(a) * P + own : size_t(abar) * P + src;  // kPullFlip
+    if (mode == kLocal) return slot<Q>(a, own, S);
+    if (mode == kPull) return wall ? slot<Q>(abar, own, S) : slot<Q>(a, src, S);
+    return wall ? slot<Q>(a, own, S) : slot<Q>(abar, src, S);  // kPullFlip
 }
 
 // Loads and stores of population elements.  NT marks an access
@@ -324,7 +336,7 @@ __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restri
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     if (WALLS && is_solid(p.g, x, y, z)) return;
-    const size_t P = p.g.P;
+    const int TS = p.g.S;
     const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
     unsigned idx[Q];
     bool wall[Q];
@@ -334,13 +346,13 @@ __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restri
         constexpr int a = decltype(ac)::value;
         constexpr int abar = Lattice<D>::opp(a);
         constexpr bool aligned = kLattice<D>.e[a][0] == 0;
-        const S* ptr = (WALLS && wall[a]) ? src + size_t(abar) * P + own : src + size_t(a) * P + idx[a];
+        const S* ptr = src + ((WALLS && wall[a]) ? slot<Q>(abar, own, TS) : slot<Q>(a, idx[a], TS));
         f[a] = Store<S>::load(get<NT && aligned>(ptr));
     });
     collide<D, C, FORCE>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        put<NT>(dst + size_t(a) * P + own, Store<S>::save(f[a]));
+        put<NT>(dst + slot<Q>(a, own, TS), Store<S>::save(f[a]));
     });
 }
 
@@ -354,17 +366,17 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_even(S* __restrict__ A,
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     if (WALLS && is_solid(p.g, x, y, z)) return;
-    const size_t P = p.g.P;
+    const int TS = p.g.S;
     const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
     C f[Q];
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        f[a] = Store<S>::load(get<NT>(A + size_t(a) * P + own));
+        f[a] = Store<S>::load(get<NT>(A + slot<Q>(a, own, TS)));
     });
     collide<D, C, FORCE>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        put<NT>(A + size_t(Lattice<D>::opp(a)) * P + own, Store<S>::save(f[a]));
+        put<NT>(A + slot<Q>(Lattice<D>::opp(a), own, TS), Store<S>::save(f[a]));
     });
 }
 
@@ -380,7 +392,7 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_odd(S* __restrict__ A,
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     if (WALLS && is_solid(p.g, x, y, z)) return;
-    const size_t P = p.g.P;
+    const int TS = p.g.S;
     const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
     unsigned idx[Q];
     bool wall[Q];
@@ -389,7 +401,7 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_odd(S* __restrict__ A,
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         constexpr int abar = Lattice<D>::opp(a);
-        off[a] = (WALLS && wall[a]) ? size_t(a) * P + own : size_t(abar) * P + idx[a];
+        off[a] = (WALLS && wall[a]) ? slot<Q>(a, own, TS) : slot<Q>(abar, idx[a], TS);
     });
     C f[Q];
     static_for<Q>([&](auto ac) {
@@ -455,7 +467,7 @@ __global__ __launch_bounds__(256) void k_import(S* __restrict__ A, const double*
         constexpr int a = decltype(ac)::value;
         double v = fn[a];
         if constexpr (Store<S>::kDeviation) v -= kLattice<D>.w[a];
-        A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.P)] =
+        A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.S)] =
             Store<S>::save(typename Store<S>::C(v));
     });
 }
@@ -472,7 +484,7 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ A, const IoArg
     link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        f[a] = Store<S>::load(A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.P)]);
+        f[a] = Store<S>::load(A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.S)]);
     });
 }
 

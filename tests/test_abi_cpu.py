@@ -76,8 +76,10 @@ def test_create_accepts_and_sizes():
         for storage, size in ((lbm.F64, 8), (lbm.F32, 4), (lbm.F16_DEV, 2), (lbm.BF16_DEV, 2)):
             st, h = _create(lattice=lattice, nx=7, ny=6, nz=nz, storage=storage)
             assert st == lbm.OK
-            plane = -(-7 * 6 * nz // 128) * 128  # planes padded to 128 elements
-            assert L.lbm_buffer_bytes(h) == Q * plane * size
+            N = 7 * 6 * nz
+            T = min(4096, 1 << (N - 1).bit_length())  # tile length: power of two, <= 4096
+            want = -(-N // T) * T * Q * size
+            assert L.lbm_buffer_bytes(h) == -(-want // 256) * 256
             assert L.lbm_buffer_bytes(h) % 256 == 0
             assert L.lbm_adjoint_workspace_bytes(h, 1) > 0
             assert L.lbm_adjoint_workspace_bytes(h, 5) - L.lbm_adjoint_workspace_bytes(h, 4) == \

@@ -20,9 +20,10 @@
 // and du/df_b = e_b, du/dF = I/2, domega/dtau = -omega^2.  The same
 // expressions hold for the deviation storages (the update is affine in f).
 //
-// lambda fields are canonical [Q][N] arrays in the arithmetic type of the
-// storage.  taubar and Fbar accumulate per workgroup in FP64 into a fixed
-// slot per workgroup, summed at the end in a fixed order.
+// lambda fields use the tiled layout of the stored state (slot()) in the
+// arithmetic type of the storage, with the same streaming hints as the
+// forward step.  taubar and Fbar accumulate per workgroup in FP64 into a
+// fixed slot per workgroup, summed at the end in a fixed order.
 #pragma once
 
 #include "kernels.hpp"
@@ -62,7 +63,7 @@ __device__ __forceinline__ void block_accumulate(double (&v)[kAccSlots], double*
 // One adjoint step: reads the forward state g^n (two-lattice layout) and
 // lambda^{n+1}, writes lambda^n, accumulates taubar and Fbar.
 template <int D, class S, bool WALLS, bool FORCE>
-__global__ __launch_bounds__(256) void k_adjoint_step(const S* __restrict__ g,
+__global__ LBM_STEP_BOUNDS void k_adjoint_step(const S* __restrict__ g,
                                                       const typename Store<S>::C* __restrict__ lam_in,
                                                       typename Store<S>::C* __restrict__ lam_out,
                                                       double* __restrict__ acc,
@@ -75,10 +76,10 @@ __global__ __launch_bounds__(256) void k_adjoint_step(const S* __restrict__ g,
     const bool active = inside && !(WALLS && is_solid(p.g, x, y, z));
     double part[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
     if (inside) {
-        const unsigned N = p.g.N;
+        const int TS = p.g.S;
         const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
         if (!active) {
-            for (int a = 0; a < Q; ++a) lam_out[size_t(a) * N + own] = C(0);
+            for (int a = 0; a < Q; ++a) lam_out[slot<Q>(a, own, TS)] = C(0);
         } else {
             unsigned idx[Q];
             bool wall[Q];
@@ -88,14 +89,16 @@ __global__ __launch_bounds__(256) void k_adjoint_step(const S* __restrict__ g,
             static_for<Q>([&](auto ac) {
                 constexpr int a = decltype(ac)::value;
                 constexpr int abar = Lattice<D>::opp(a);
-                ls[a] = (WALLS && wall[a]) ? lam_in[size_t(abar) * N + own] : lam_in[size_t(a) * N + idx[a]];
+                constexpr bool aligned = kLattice<D>.e[a][0] == 0;
+                ls[a] = get<aligned>(lam_in + ((WALLS && wall[a]) ? slot<Q>(abar, own, TS) : slot<Q>(a, idx[a], TS)));
             });
             // f^n: pull from x - e_a in the stored state.
             link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
             C f[Q];
             static_for<Q>([&](auto ac) {
                 constexpr int a = decltype(ac)::value;
-                f[a] = Store<S>::load(g[gather_offset<D>(kPull, a, own, idx[a], WALLS && wall[a], p.g.S)]);
+                constexpr bool aligned = kLattice<D>.e[a][0] == 0;
+                f[a] = Store<S>::load(get<aligned>(g + gather_offset<D>(kPull, a, own, idx[a], WALLS && wall[a], TS)));
             });
             const Moments<D, C> m = node_moments<D, C, FORCE>(f, p.F);
             const C usq = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
@@ -142,8 +145,8 @@ __global__ __launch_bounds__(256) void k_adjoint_step(const S* __restrict__ g,
             static_for<Q>([&](auto ac) {
                 constexpr int b = decltype(ac)::value;
                 constexpr int ex = kLattice<D>.e[b][0], ey = kLattice<D>.e[b][1], ez = kLattice<D>.e[b][2];
-                lam_out[size_t(b) * N + own] =
-                    keep * ls[b] + base + (eterm<ex>(V[0]) + eterm<ey>(V[1]) + eterm<ez>(V[2]));
+                put<true>(lam_out + slot<Q>(b, own, TS),
+                          C(keep * ls[b] + base + (eterm<ex>(V[0]) + eterm<ey>(V[1]) + eterm<ez>(V[2]))));
             });
             part[0] = -double(p.omega) * double(p.omega) * double(tsum);
             for (int d = 0; d < D; ++d) part[1 + d] = double(A[d]) + 0.5 * double(p.half) * double(B[d]);
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(256) void k_adjoint_seed(const double* __restrict__
         static_for<Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             constexpr auto& L = kLattice<D>;
-            lam[size_t(a) * N + own] =
+            lam[slot<Q>(a, own, g.S)] =
                 C(eterm<L.e[a][0]>(ub[0]) + eterm<L.e[a][1]>(ub[1]) + eterm<L.e[a][2]>(ub[2]));
         });
         for (int d = 0; d < D; ++d) part[1 + d] = 0.5 * ub[d];
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(256) void k_adjoint_init_map(const typename Store<S
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         constexpr auto& L = kLattice<D>;
-        const double wl = L.w[a] * double(lam[size_t(a) * N + own]);
+        const double wl = L.w[a] * double(lam[slot<Q>(a, own, g.S)]);
         const double edu = eterm<L.e[a][0]>(u[0]) + eterm<L.e[a][1]>(u[1]) + eterm<L.e[a][2]>(u[2]);
         m0 += wl;
         m1[0] += eterm<L.e[a][0]>(wl);

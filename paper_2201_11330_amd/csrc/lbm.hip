@@ -476,8 +476,8 @@ WorkspaceLayout workspace_layout(const lbm_ctx* c, int k)
     L.acc_doubles = L.nblocks * kAccSlots;
     L.seg = 0;
     L.lam0 = L.seg + size_t(k > 1 ? k - 1 : 0) * L.state_bytes;
-    L.lam1 = L.lam0 + round256(size_t(c->Q) * c->N * celem);
-    L.acc = L.lam1 + round256(size_t(c->Q) * c->N * celem);
+    L.lam1 = L.lam0 + round256(c->state_elems * celem);
+    L.acc = L.lam1 + round256(c->state_elems * celem);
     L.result = L.acc + round256(L.acc_doubles * sizeof(double));
     L.total = L.result + 256;
     return L;

@@ -64,6 +64,18 @@ def uniform_noise(shape, amplitude, seed):
     return rng.uniform(-amplitude, amplitude, size=shape)
 
 
+def uniform_noise_device(shape, amplitude, seed, device="cuda"):
+    """Independent U(-A, +A) values generated on a device with torch's seeded
+    generator (for fields too large to build on the host)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    t = torch.empty(shape, dtype=torch.float64, device=device)
+    t.uniform_(-amplitude, amplitude, generator=g)
+    return t
+
+
 def population_noise(lattice, dims, amplitude, seed):
     """Perturbation added to every population of every node, [Q][z][y][x]."""
     nx, ny, nz = dims

@@ -144,3 +144,51 @@ def test_reduced_precision_taylor_green_512():
         torch.cuda.empty_cache()
         bound = {"f32": (1e-4, 1e-2), "f16": (5e-2, 1.0), "bf16": (0.25, 10.0)}[storage]
         assert du / U0 < bound[0] and rerr < bound[1]
+
+
+@pytest.mark.slow
+def test_maximum_size_box_sampled():
+    """Largest box the 32-bit node index admits at this size class:
+    1280^3 = 2.1e9 nodes (< 2^31), D3Q19 FP16 storage with the in-place AA
+    pattern (80 GB; element offsets up to 4e10, beyond 2^32).  Random
+    velocities (U(+-0.02) per component per node, so a wrong neighbour index
+    shows as an O(0.02) error, far above FP16 rounding), two steps (one even,
+    one odd), then u at sampled nodes -- corners and seams included -- against
+    the oracle on each node's dependency window."""
+    n, steps, tau = 1280, 2, 0.7
+    N = n ** 3
+    assert N < 2 ** 31
+    sim = lbm.LBM(lbm.D3Q19, n, n, n, tau, storage="f16", aa=True)
+    rho = torch.ones((n, n, n), dtype=torch.float64, device="cuda")
+    u = W.uniform_noise_device((3, n, n, n), 0.02, seed=13)
+    sim.init_equilibrium(rho, u)
+    centers = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 0), (n - 1, 0, n - 1),
+               (640, 640, 640), (1, 1279, 1278), (1023, 511, 1279)]
+    windows = []
+    for (cx, cy, cz) in centers:
+        ix = [(cx + d) % n for d in range(-steps, steps + 1)]
+        iy = [(cy + d) % n for d in range(-steps, steps + 1)]
+        iz = [(cz + d) % n for d in range(-steps, steps + 1)]
+        ti = lambda v: torch.tensor(v, device="cuda")
+        uw = u[:, ti(iz)][:, :, ti(iy)][:, :, :, ti(ix)].cpu().numpy()
+        windows.append(uw)
+    sim._keep = None
+    del rho, u
+    torch.cuda.empty_cache()
+    sim.step(steps)
+    red = sim.reduce()
+    assert not red["unstable"]
+    _, ug = sim.moments(dtype=torch.float32)
+    worst = 0.0
+    for (cx, cy, cz), uw in zip(centers, windows):
+        w = 2 * steps + 1
+        ref = oracle.Sim(oracle.D3Q19, w, w, w, tau=tau)
+        ref.init_equilibrium(np.ones((w, w, w)), uw)
+        ref.step(steps)
+        _, ur = ref.moments()
+        got = ug[:, cz, cy, cx].double().cpu().numpy()
+        worst = max(worst, np.abs(got - ur[:, steps, steps, steps]).max())
+    print(f"1280^3 FP16 AA: worst |u - u_oracle| at sampled nodes {worst:.2e}, "
+          f"mass {red['mass']:.6e} (N = {N})")
+    assert worst < 2e-4  # FP16 rounding of f - w is ~1e-5 here; an index error is ~2e-2
+    assert abs(red["mass"] / N - 1) < 1e-6

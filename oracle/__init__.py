@@ -15,9 +15,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-D2Q9, D3Q19 = 0, 1
+D2Q9, D3Q19, D3Q27 = 0, 1, 2
 PERIODIC, SOLID_ENDS, WALLS_OUTSIDE = 0, 1, 2
-_QOF = {D2Q9: 9, D3Q19: 19}
+_QOF = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -53,6 +53,8 @@ def _load():
     lib.orc_adjoint.argtypes = (
         [ctypes.c_int] * 4 + [ctypes.c_double, _dp, _ip, _dp, _dp, _dp, ctypes.c_int, _dp, _dp,
                               _dp, _dp])
+    lib.orc_set_solid.argtypes = [vp, ctypes.POINTER(ctypes.c_ubyte)]
+    lib.orc_wall_force.argtypes = [vp, _dp]
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -97,8 +99,8 @@ def lattice_tables(lattice):
     """(e [Q,3] int, t [Q] float64) of the oracle's lattice."""
     lib = _load()
     Q, D = ctypes.c_int(), ctypes.c_int()
-    e = np.zeros((19, 3), dtype=np.int32)
-    t = np.zeros(19)
+    e = np.zeros((27, 3), dtype=np.int32)
+    t = np.zeros(27)
     _check(lib.orc_lattice_tables(lattice, ctypes.byref(Q), ctypes.byref(D),
                                   e.ctypes.data_as(_ip), _d(t)), "lattice_tables")
     return e[: Q.value].astype(np.int64), t[: Q.value].copy()
@@ -190,6 +192,18 @@ class Sim:
         _check(self._lib.orc_geometry(self._h, g.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))),
                "geometry")
         return g.astype(bool)
+
+    def set_solid(self, solid):
+        """Solid mask [z][y][x] (nonzero = solid), before initialisation."""
+        m = np.ascontiguousarray(np.asarray(solid).reshape(self.shape), dtype=np.uint8)
+        _check(self._lib.orc_set_solid(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))),
+               "set_solid")
+
+    def wall_force(self):
+        """Momentum-exchange force on all walls during the last propagation."""
+        F = np.zeros(3)
+        _check(self._lib.orc_wall_force(self._h, _d(F)), "wall_force")
+        return F
 
     def reduce(self):
         m, k, um = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -28,7 +28,7 @@
 
 #include "oracle.h"
 
-#define ORC_QMAX 19
+#define ORC_QMAX 27
 #define ORC_RHO0 1.0 /* constant density of the incompressible model (Table 3) */
 
 typedef struct {
@@ -60,6 +60,22 @@ static const double D3Q19_T[19] = {
     1.0 / 36, 1.0 / 18, 1.0 / 3,  1.0 / 18, 1.0 / 36, 1.0 / 18, 1.0 / 36,
     1.0 / 36, 1.0 / 36, 1.0 / 18, 1.0 / 36, 1.0 / 36};
 
+/*
+ * D3Q27 (the paper's validation lattice, Sec. 5): all of {-1,0,1}^3 in the
+ * same lexicographic order (e_x slowest), so the opposite of a is 26 - a.
+ * Weights: rest 8/27, faces 2/27, edges 1/54, corners 1/216.
+ */
+static const int D3Q27_E[27][3] = {
+    {-1, -1, -1}, {-1, -1, 0}, {-1, -1, 1}, {-1, 0, -1}, {-1, 0, 0}, {-1, 0, 1},
+    {-1, 1, -1},  {-1, 1, 0},  {-1, 1, 1},  {0, -1, -1}, {0, -1, 0}, {0, -1, 1},
+    {0, 0, -1},   {0, 0, 0},   {0, 0, 1},   {0, 1, -1},  {0, 1, 0},  {0, 1, 1},
+    {1, -1, -1},  {1, -1, 0},  {1, -1, 1},  {1, 0, -1},  {1, 0, 0},  {1, 0, 1},
+    {1, 1, -1},   {1, 1, 0},   {1, 1, 1}};
+static const double D3Q27_T[27] = {
+    1.0 / 216, 1.0 / 54, 1.0 / 216, 1.0 / 54, 2.0 / 27, 1.0 / 54, 1.0 / 216, 1.0 / 54, 1.0 / 216,
+    1.0 / 54,  2.0 / 27, 1.0 / 54,  2.0 / 27, 8.0 / 27, 2.0 / 27, 1.0 / 54,  2.0 / 27, 1.0 / 54,
+    1.0 / 216, 1.0 / 54, 1.0 / 216, 1.0 / 54, 2.0 / 27, 1.0 / 54, 1.0 / 216, 1.0 / 54, 1.0 / 216};
+
 static int make_lattice(int lattice, orc_lattice* L)
 {
     memset(L, 0, sizeof(*L));
@@ -83,6 +99,15 @@ static int make_lattice(int lattice, orc_lattice* L)
         }
         return 0;
     }
+    if (lattice == ORC_D3Q27) {
+        L->Q = 27;
+        L->D = 3;
+        for (int a = 0; a < 27; ++a) {
+            for (int d = 0; d < 3; ++d) L->e[a][d] = D3Q27_E[a][d];
+            L->t[a] = D3Q27_T[a];
+        }
+        return 0;
+    }
     return ORC_EINVAL;
 }
 
@@ -100,6 +125,20 @@ static int opposite(const orc_lattice* L, int a) { return L->Q - 1 - a; }
 #include "node.inc"
 #undef T
 #undef SFX
+
+/* Neumaier's compensated summation. */
+typedef struct {
+    double sum, comp;
+} kahan;
+static void kahan_add(kahan* k, double v)
+{
+    double t = k->sum + v;
+    if (fabs(k->sum) >= fabs(v))
+        k->comp += (k->sum - t) + v;
+    else
+        k->comp += (v - t) + k->sum;
+    k->sum = t;
+}
 
 struct orc_sim {
     orc_lattice L;
@@ -330,18 +369,54 @@ int orc_geometry(const orc_sim* s, unsigned char* geo)
     return 0;
 }
 
-/* Neumaier's compensated summation. */
-typedef struct {
-    double sum, comp;
-} kahan;
-static void kahan_add(kahan* k, double v)
+/*
+ * SetGeometry with a user solid mask (Sec. 3.3: geo is 1 on fluid and 0 on
+ * solid nodes): a node is fluid when it is not on a solid end plane and
+ * solid[id] == 0.  Call before initialising the populations.
+ */
+int orc_set_solid(orc_sim* s, const unsigned char* solid)
 {
-    double t = k->sum + v;
-    if (fabs(k->sum) >= fabs(v))
-        k->comp += (k->sum - t) + v;
-    else
-        k->comp += (v - t) + k->sum;
-    k->sum = t;
+    for (int z = 0; z < s->nz; ++z)
+        for (int y = 0; y < s->ny; ++y)
+            for (int x = 0; x < s->nx; ++x) {
+                int c[3] = {x, y, z}, n[3] = {s->nx, s->ny, s->nz};
+                unsigned char fluid = 1;
+                for (int d = 0; d < 3; ++d)
+                    if (s->bc[d] == ORC_SOLID_ENDS && (c[d] == 0 || c[d] == n[d] - 1)) fluid = 0;
+                long id = node_id(s, x, y, z);
+                if (solid[id]) fluid = 0;
+                s->geo[id] = fluid;
+            }
+    return 0;
+}
+
+/*
+ * Momentum-exchange force on the walls during the last propagation
+ * (Sec. 4, drag evaluation): for every fluid node x and outgoing direction
+ * a whose neighbour x + e_a is a wall, the population f*_a(x) that left and
+ * the population f_abar(x) that came back carry momentum to the wall:
+ *   F = sum_x sum_a [f*_a(x, t) + f_abar(x, t + dt)] e_a.
+ * Reading: with the link-wise bounce-back the returning population is the
+ * one at x after the propagation (the paper writes it at the wall-side
+ * node of the nodal scheme).
+ */
+int orc_wall_force(const orc_sim* s, double F[3])
+{
+    const int Q = s->L.Q;
+    kahan acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int z = 0; z < s->nz; ++z)
+        for (int y = 0; y < s->ny; ++y)
+            for (int x = 0; x < s->nx; ++x) {
+                long id = node_id(s, x, y, z);
+                if (!s->geo[id]) continue;
+                for (int a = 0; a < Q; ++a) {
+                    if (neighbour(s, x, y, z, a, +1) >= 0) continue;
+                    double m = s->fb[id * Q + a] + s->f[id * Q + opposite(&s->L, a)];
+                    for (int d = 0; d < 3; ++d) kahan_add(&acc[d], m * (double)s->L.e[a][d]);
+                }
+            }
+    for (int d = 0; d < 3; ++d) F[d] = acc[d].sum + acc[d].comp;
+    return 0;
 }
 
 /*

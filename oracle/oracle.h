@@ -16,7 +16,7 @@
 extern "C" {
 #endif
 
-enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1 };
+enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1, ORC_D3Q27 = 2 };
 enum { ORC_PERIODIC = 0, ORC_SOLID_ENDS = 1, ORC_WALLS_OUTSIDE = 2 };
 enum { ORC_EINVAL = -1, ORC_ENOMEM = -2 };
 
@@ -31,6 +31,8 @@ int orc_get_populations(const orc_sim* s, double* f);
 int orc_step(orc_sim* s, int n);
 int orc_moments(const orc_sim* s, double* rho, double* u);
 int orc_geometry(const orc_sim* s, unsigned char* geo);
+int orc_set_solid(orc_sim* s, const unsigned char* solid);
+int orc_wall_force(const orc_sim* s, double F[3]);
 int orc_reduce(const orc_sim* s, double* mass, double* ke, double* umax, long* nonfinite);
 
 int orc_num_threads(void);

@@ -38,7 +38,7 @@ def test_d2q9_tables_match_the_paper():
         assert t[a] == tt
 
 
-@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19])
+@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19, oracle.D3Q27])
 def test_lattice_symmetry_and_isotropy(lattice):
     """Opposite index m-1-a (Sec. 2.1) and the moment conditions that make the
     weights of Qian's DdQm models: sum t = 1, sum t e = 0, sum t e e = I/3,
@@ -60,6 +60,17 @@ def test_lattice_symmetry_and_isotropy(lattice):
     assert np.abs(four - iso).max() < 1e-15
 
 
+def test_d3q27_velocity_set_and_weights():
+    """D3Q27 = all of {-1,0,1}^3 in lexicographic order (e_x slowest), with
+    the tensor-product weights (2/3, 1/6, 1/6)^3: 8/27, 2/27, 1/54, 1/216."""
+    e, t = oracle.lattice_tables(oracle.D3Q27)
+    want = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+    assert [tuple(v) for v in e] == want
+    w1 = {0: 2 / 3, 1: 1 / 6, -1: 1 / 6}
+    for a, v in enumerate(e):
+        assert abs(t[a] - w1[v[0]] * w1[v[1]] * w1[v[2]]) < 1e-17
+
+
 def test_d3q19_velocity_set_is_the_qian_set():
     """D3Q19 = rest + 6 faces + 12 edges of {-1,0,1}^3 (no corners), each once,
     in the lexicographic order (e_x slowest) that extends the D2Q9 numbering."""
@@ -72,7 +83,7 @@ def test_d3q19_velocity_set_is_the_qian_set():
         assert t[a] == {0: 1 / 3, 1: 1 / 18, 2: 1 / 36}[n]
 
 
-@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19])
+@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19, oracle.D3Q27])
 def test_incompressible_equilibrium_moments(lattice):
     """The incompressible equilibrium of Eq. (incompressible_feq) has
     sum feq = p/c_s^2, sum e feq = rho0 u and sum e e feq = (p/c_s^2) c_s^2 I
@@ -101,7 +112,7 @@ def _random_pops(lattice, rng, amp=0.01):
     return oracle.equilibrium_node(lattice, 1.0, u) + amp * t * rng.standard_normal(len(t))
 
 
-@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19])
+@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19, oracle.D3Q27])
 @pytest.mark.parametrize("tau", [0.51, 0.6, 0.8, 1.0, 1.7])
 def test_collision_conserves_mass_and_adds_F_momentum(lattice, tau):
     """Pin P1: the collision keeps sum f exactly and changes sum e f by exactly
@@ -122,7 +133,7 @@ def test_collision_conserves_mass_and_adds_F_momentum(lattice, tau):
         assert np.abs((ef.T @ fb0) - (ef.T @ f)).max() <= 2e-16
 
 
-@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19])
+@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19, oracle.D3Q27])
 def test_collision_relaxes_toward_equilibrium(lattice):
     """Eq. (collision): the non-equilibrium part is scaled by (1 - omega) and
     equilibrium is a fixed point (pin P2)."""
@@ -144,7 +155,7 @@ def test_collision_relaxes_toward_equilibrium(lattice):
         assert np.abs(fb - (feq + (1 - 1 / tau) * neq)).max() < 2e-16
 
 
-@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19])
+@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19, oracle.D3Q27])
 def test_complex_collision_matches_real(lattice):
     """The complex instantiation used for derivatives equals the real one
     when imaginary parts are zero, and a complex step gives the directional
@@ -170,13 +181,14 @@ def _equilibrium_state(lattice, dims, rho, u):
     return s.get_populations()
 
 
-@pytest.mark.parametrize("lattice,dims", [(oracle.D2Q9, (9, 7, 1)), (oracle.D3Q19, (6, 5, 4))])
+@pytest.mark.parametrize("lattice,dims", [(oracle.D2Q9, (9, 7, 1)), (oracle.D3Q19, (6, 5, 4)),
+                                          (oracle.D3Q27, (5, 4, 6))])
 def test_pure_streaming_is_a_shift(lattice, dims):
     """Pin P4: with omega = 0 (tau = +inf) and F = 0 one step is exactly
     Eq. (propagation): f_a(x, t) = f_a(x - e_a, t - 1) with periodic wrap."""
     rng = np.random.default_rng(1)
     nx, ny, nz = dims
-    Q = 9 if lattice == oracle.D2Q9 else 19
+    Q = {oracle.D2Q9: 9, oracle.D3Q19: 19, oracle.D3Q27: 27}[lattice]
     e, _ = oracle.lattice_tables(lattice)
     f0 = rng.uniform(0.0, 0.1, size=(Q, nz, ny, nx))
     s = oracle.Sim(lattice, nx, ny, nz, tau=math.inf)
@@ -231,13 +243,14 @@ def test_pure_streaming_with_walls_is_a_reflecting_permutation(bc):
     assert np.array_equal(s.get_populations(), f)
 
 
-@pytest.mark.parametrize("lattice,dims", [(oracle.D2Q9, (8, 6, 1)), (oracle.D3Q19, (5, 6, 4))])
+@pytest.mark.parametrize("lattice,dims", [(oracle.D2Q9, (8, 6, 1)), (oracle.D3Q19, (5, 6, 4)),
+                                          (oracle.D3Q27, (4, 5, 3))])
 def test_uniform_equilibrium_is_a_fixed_point(lattice, dims):
     """Pin P3: a uniform equilibrium is left unchanged by a periodic step."""
     nx, ny, nz = dims
     u = np.zeros((3, nz, ny, nx))
     u[0], u[1] = 0.03, -0.02
-    if lattice == oracle.D3Q19:
+    if lattice != oracle.D2Q9:
         u[2] = 0.01
     rho = np.full((nz, ny, nx), 1.02)
     s = oracle.Sim(lattice, nx, ny, nz, tau=0.7)
@@ -412,7 +425,7 @@ def _poiseuille(H_walls, ny, g, tau):
     return g / (2 * nu) * (y - y1) * (y2 - y) + g * (16 * lam - 3) / (24 * nu)
 
 
-@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19])
+@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19, oracle.D3Q27])
 @pytest.mark.parametrize("tau", [0.6, 0.9, 0.5 + math.sqrt(3 / 16), 1.5])
 @pytest.mark.parametrize("walls", [oracle.SOLID_ENDS, oracle.WALLS_OUTSIDE])
 def test_poiseuille_closed_form(lattice, tau, walls):
@@ -460,6 +473,7 @@ def test_adjoint_closed_form_mean_velocity():
     (oracle.D2Q9, (5, 8, 1), (0, 1, 0)),
     (oracle.D3Q19, (4, 6, 5), (0, 1, 0)),
     (oracle.D3Q19, (5, 4, 4), (2, 0, 1)),
+    (oracle.D3Q27, (4, 5, 4), (0, 1, 2)),
 ])
 def test_adjoint_matches_complex_step_tangent(lattice, dims, bc):
     """Pin P13: the transposed run (complex-step Jacobians of each collision,
@@ -476,7 +490,7 @@ def test_adjoint_matches_complex_step_tangent(lattice, dims, bc):
     u_tgt[:D] = 0.03 * rng.standard_normal((D, nz, ny, nx))
     F = np.zeros(3)
     F[:D] = [2e-5, -1e-5, 3e-5][:D]
-    Q = 9 if lattice == oracle.D2Q9 else 19
+    Q = {oracle.D2Q9: 9, oracle.D3Q19: 19, oracle.D3Q27: 27}[lattice]
     noise = 1e-4 * rng.standard_normal((Q, nz, ny, nx))
     tau, N = 0.8, 9
     s = oracle.Sim(lattice, *dims, tau=tau, force=F, bc=bc)
@@ -523,3 +537,78 @@ def test_objective_finite_difference():
 
     fd = (J(1) - J(-1)) / (2 * eps)
     assert abs(fd - dJ) < 1e-7 * abs(dJ)
+
+
+def _box_mask(dims, lo, hi):
+    nx, ny, nz = dims
+    m = np.zeros((nz, ny, nx), dtype=np.uint8)
+    m[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = 1
+    return m
+
+
+def test_solid_mask_equals_solid_end_planes():
+    """A user mask marking the first and last y planes gives exactly the same
+    run as the solid-ends boundary (SetGeometry with a geo array)."""
+    dims = (6, 9, 5)
+    nx, ny, nz = dims
+    rho, u, noise = _tg3(dims)
+    a = oracle.Sim(oracle.D3Q19, *dims, tau=0.8, force=(1e-5, 0, 0), bc=(0, 1, 0))
+    b = oracle.Sim(oracle.D3Q19, *dims, tau=0.8, force=(1e-5, 0, 0))
+    m = np.zeros((nz, ny, nx), dtype=np.uint8)
+    m[:, 0, :] = m[:, -1, :] = 1
+    b.set_solid(m)
+    assert np.array_equal(a.geometry(), b.geometry())
+    for s in (a, b):
+        s.init_equilibrium(rho, u, noise)
+        s.step(7)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    assert np.array_equal(a.wall_force(), b.wall_force())
+
+
+@pytest.mark.parametrize("lattice", [oracle.D3Q19, oracle.D3Q27])
+def test_pure_streaming_around_an_obstacle_is_a_permutation(lattice):
+    dims = (7, 6, 5)
+    Q = 19 if lattice == oracle.D3Q19 else 27
+    s = oracle.Sim(lattice, *dims, tau=math.inf)
+    s.set_solid(_box_mask(dims, (2, 2, 1), (4, 4, 3)))
+    fluid = s.geometry()
+    f0 = np.random.default_rng(3).uniform(0, 0.1, size=(Q,) + fluid.shape) * fluid
+    s.set_populations(f0)
+    s.step(3)
+    f = s.get_populations()
+    assert np.array_equal(np.sort(f[:, fluid].ravel()), np.sort(f0[:, fluid].ravel()))
+
+
+@pytest.mark.parametrize("lattice", [oracle.D2Q9, oracle.D3Q19, oracle.D3Q27])
+@pytest.mark.parametrize("walls", [oracle.SOLID_ENDS, oracle.WALLS_OUTSIDE])
+def test_wall_force_balances_body_force_in_a_channel(lattice, walls):
+    """Momentum balance (Sec. 4 momentum exchange): at steady state the walls
+    take exactly the momentum the body force puts in, V_fluid * g per step."""
+    ny, g, tau = 14, 1e-6, 0.8
+    nz = 1 if lattice == oracle.D2Q9 else 2
+    s = oracle.Sim(lattice, 3, ny, nz, tau=tau, force=(g, 0, 0), bc=(0, walls, 0))
+    fluid = s.geometry()
+    s.init_equilibrium(np.ones(fluid.shape), np.zeros((3,) + fluid.shape))
+    H = ny - 2 if walls == oracle.SOLID_ENDS else ny
+    s.step(int(math.log(1e12) / ((tau - 0.5) / 3 * (math.pi / H) ** 2)))
+    F = s.wall_force()
+    V = fluid.sum()
+    assert abs(F[0] / (V * g) - 1) < 1e-9
+    assert np.abs(F[1:]).max() < 1e-9 * V * g
+
+
+@pytest.mark.parametrize("lattice", [oracle.D3Q19, oracle.D3Q27])
+def test_wall_force_on_an_obstacle_balances_body_force(lattice):
+    """A block obstacle in a periodic box driven by a body force: at steady
+    state the drag on the obstacle equals V_fluid * g (the only walls)."""
+    dims = (8, 7, 6)
+    g, tau = 1e-6, 0.9
+    s = oracle.Sim(lattice, *dims, tau=tau, force=(g, 0, 0))
+    s.set_solid(_box_mask(dims, (3, 2, 2), (5, 5, 4)))
+    fluid = s.geometry()
+    s.init_equilibrium(np.ones(fluid.shape), np.zeros((3,) + fluid.shape))
+    s.step(6000)
+    F = s.wall_force()
+    V = fluid.sum()
+    assert abs(F[0] / (V * g) - 1) < 1e-8
+    assert np.abs(F[1:]).max() < 1e-8 * V * g

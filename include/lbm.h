@@ -64,10 +64,11 @@ typedef enum {
 } lbm_status;
 
 /* Discrete velocity models of Sec. 2.1.  D2Q9 is numbered as printed there
- * (lexicographic in (e_x, e_y), e_x slowest); D3Q19 extends that rule to
- * three dimensions without the 8 corners.  In both the opposite of a is
+ * (lexicographic in (e_x, e_y), e_x slowest); D3Q27 extends that rule to
+ * all of {-1,0,1}^3 (the lattice of the paper's validation case, Sec. 5) and
+ * D3Q19 is that order without the 8 corners.  In each the opposite of a is
  * Q - 1 - a. */
-typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 } lbm_lattice;
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_lattice;
 
 /* Storage of the populations in device memory.  LBM_F64 stores f and
  * computes in FP64 (the paper's precision).  The others store the deviation
@@ -160,6 +161,29 @@ lbm_status lbm_moments(lbm_ctx* ctx, void* rho, void* u, int out_is_f32);
  * written) when a population is NaN or infinite.
  */
 lbm_status lbm_reduce(lbm_ctx* ctx, double* mass, double* kinetic_energy, double* umax);
+
+/*
+ * SetGeometry with a solid mask (Sec. 3.3: the geo array marks fluid and
+ * solid nodes): solid[id] != 0 makes node id solid, in addition to the solid
+ * end planes of LBM_SOLID_ENDS axes.  Every link from a fluid node into a
+ * solid node bounces back halfway (Eq. (bb)).  solid: device uint8 [N].
+ * Call after lbm_bind and before initialising the populations (the state
+ * becomes undefined); not after a graph was captured (LBM_ESTATE).  The
+ * library allocates 4 bytes per node for per-node link bits (freed by
+ * lbm_destroy) and the step kernels read them: 4 more bytes per update.
+ * Asynchronous on the bound stream.
+ */
+lbm_status lbm_set_solid(lbm_ctx* ctx, const unsigned char* solid);
+
+/*
+ * Momentum-exchange force on all walls (solid nodes and the box walls)
+ * during the last propagation, the drag evaluation of Sec. 4:
+ * F = sum over fluid x and directions a with x + e_a a wall of
+ * [f*_a(x, t) + f_abar(x, t + 1)] e_a = 2 f_abar(x, t + 1) e_a (the
+ * population that came back is the one that left).  Host output [3],
+ * accumulated in FP64 in a fixed order.  Synchronises the bound stream.
+ */
+lbm_status lbm_wall_force(lbm_ctx* ctx, double force[3]);
 
 /* Time steps taken since the last init/set (the AA parity is its low bit). */
 long long lbm_steps_taken(const lbm_ctx* ctx);

@@ -62,7 +62,7 @@ __device__ __forceinline__ void block_accumulate(double (&v)[kAccSlots], double*
 
 // One adjoint step: reads the forward state g^n (two-lattice layout) and
 // lambda^{n+1}, writes lambda^n, accumulates taubar and Fbar.
-template <int D, class S, bool WALLS, bool FORCE>
+template <int L, class S, bool WALLS, bool FORCE>
 __global__ LBM_STEP_BOUNDS void k_adjoint_step(const S* __restrict__ g,
                                                       const typename Store<S>::C* __restrict__ lam_in,
                                                       typename Store<S>::C* __restrict__ lam_out,
@@ -70,7 +70,7 @@ __global__ LBM_STEP_BOUNDS void k_adjoint_step(const S* __restrict__ g,
                                                       AdjArgs<typename Store<S>::C> p)
 {
     using C = typename Store<S>::C;
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     int x, y, z;
     const bool inside = node_of_item(p.g, p.bx_shift, x, y, z);
     const bool active = inside && !(WALLS && is_solid(p.g, x, y, z));
@@ -84,23 +84,23 @@ __global__ LBM_STEP_BOUNDS void k_adjoint_step(const S* __restrict__ g,
             unsigned idx[Q];
             bool wall[Q];
             // lambda*: pull from x + e_a.
-            link_nodes<D, WALLS, +1>(p.g, x, y, z, idx, wall);
+            link_nodes<L, WALLS, +1>(p.g, x, y, z, idx, wall);
             C ls[Q];
             static_for<Q>([&](auto ac) {
                 constexpr int a = decltype(ac)::value;
-                constexpr int abar = Lattice<D>::opp(a);
-                constexpr bool aligned = kLattice<D>.e[a][0] == 0;
+                constexpr int abar = Lattice<L>::opp(a);
+                constexpr bool aligned = kLattice<L>.e[a][0] == 0;
                 ls[a] = get<aligned>(lam_in + ((WALLS && wall[a]) ? slot<Q>(abar, own, TS) : slot<Q>(a, idx[a], TS)));
             });
             // f^n: pull from x - e_a in the stored state.
-            link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
+            link_nodes<L, WALLS, -1>(p.g, x, y, z, idx, wall);
             C f[Q];
             static_for<Q>([&](auto ac) {
                 constexpr int a = decltype(ac)::value;
-                constexpr bool aligned = kLattice<D>.e[a][0] == 0;
-                f[a] = Store<S>::load(get<aligned>(g + gather_offset<D>(kPull, a, own, idx[a], WALLS && wall[a], TS)));
+                constexpr bool aligned = kLattice<L>.e[a][0] == 0;
+                f[a] = Store<S>::load(get<aligned>(g + gather_offset<L>(kPull, a, own, idx[a], WALLS && wall[a], TS)));
             });
-            const Moments<D, C> m = node_moments<D, C, FORCE>(f, p.F);
+            const Moments<L, C> m = node_moments<L, C, FORCE>(f, p.F);
             const C usq = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
             C uF = C(0);
             if constexpr (FORCE) uF = m.ux * p.F[0] + m.uy * p.F[1] + m.uz * p.F[2];
@@ -109,8 +109,8 @@ __global__ LBM_STEP_BOUNDS void k_adjoint_step(const S* __restrict__ g,
             C tsum = C(0);  // sum_a l_a (feq_a - f_a - G_a/2)
             static_for<Q>([&](auto ac) {
                 constexpr int a = decltype(ac)::value;
-                constexpr int ex = kLattice<D>.e[a][0], ey = kLattice<D>.e[a][1], ez = kLattice<D>.e[a][2];
-                const C w = C(kLattice<D>.w[a]);
+                constexpr int ex = kLattice<L>.e[a][0], ey = kLattice<L>.e[a][1], ez = kLattice<L>.e[a][2];
+                const C w = C(kLattice<L>.w[a]);
                 const C wl = w * ls[a];
                 const C edu = eterm<ex>(m.ux) + eterm<ey>(m.uy) + eterm<ez>(m.uz);
                 m0 += wl;
@@ -144,12 +144,12 @@ __global__ LBM_STEP_BOUNDS void k_adjoint_step(const S* __restrict__ g,
             const C keep = C(1) - p.omega;
             static_for<Q>([&](auto ac) {
                 constexpr int b = decltype(ac)::value;
-                constexpr int ex = kLattice<D>.e[b][0], ey = kLattice<D>.e[b][1], ez = kLattice<D>.e[b][2];
+                constexpr int ex = kLattice<L>.e[b][0], ey = kLattice<L>.e[b][1], ez = kLattice<L>.e[b][2];
                 put<true>(lam_out + slot<Q>(b, own, TS),
                           C(keep * ls[b] + base + (eterm<ex>(V[0]) + eterm<ey>(V[1]) + eterm<ez>(V[2]))));
             });
             part[0] = -double(p.omega) * double(p.omega) * double(tsum);
-            for (int d = 0; d < D; ++d) part[1 + d] = double(A[d]) + 0.5 * double(p.half) * double(B[d]);
+            for (int d = 0; d < kDim<L>; ++d) part[1 + d] = double(A[d]) + 0.5 * double(p.half) * double(B[d]);
         }
     }
     block_accumulate(part, acc);
@@ -157,13 +157,13 @@ __global__ LBM_STEP_BOUNDS void k_adjoint_step(const S* __restrict__ g,
 
 // Output map: lambda^n_a = e_a . ubar (rho0 = 1) from ubar = dJ/du^n, and
 // Fbar += ubar/2 (u^n carries F/2).  Solid nodes get lambda = 0.
-template <int D, class S, bool WALLS>
+template <int L, class S, bool WALLS>
 __global__ __launch_bounds__(256) void k_adjoint_seed(const double* __restrict__ ubar,
                                                       typename Store<S>::C* __restrict__ lam,
                                                       double* __restrict__ acc, Dims g, int bx_shift)
 {
     using C = typename Store<S>::C;
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     int x, y, z;
     const bool inside = node_of_item(g, bx_shift, x, y, z);
     double part[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
@@ -173,27 +173,27 @@ __global__ __launch_bounds__(256) void k_adjoint_seed(const double* __restrict__
         const bool fluid = !(WALLS && is_solid(g, x, y, z));
         double ub[3] = {0.0, 0.0, 0.0};
         if (fluid)
-            for (int d = 0; d < D; ++d) ub[d] = ubar[size_t(d) * N + own];
+            for (int d = 0; d < kDim<L>; ++d) ub[d] = ubar[size_t(d) * N + own];
         static_for<Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            constexpr auto& L = kLattice<D>;
+            constexpr auto& LT = kLattice<L>;
             lam[slot<Q>(a, own, g.S)] =
-                C(eterm<L.e[a][0]>(ub[0]) + eterm<L.e[a][1]>(ub[1]) + eterm<L.e[a][2]>(ub[2]));
+                C(eterm<LT.e[a][0]>(ub[0]) + eterm<LT.e[a][1]>(ub[1]) + eterm<LT.e[a][2]>(ub[2]));
         });
-        for (int d = 0; d < D; ++d) part[1 + d] = 0.5 * ub[d];
+        for (int d = 0; d < kDim<L>; ++d) part[1 + d] = 0.5 * ub[d];
     }
     block_accumulate(part, acc);
 }
 
 // Init map: f^0_a = w_a (rho + 3 e.u0 + 4.5 (e.u0)^2 - 1.5 u0.u0) + noise, so
 // u0bar = sum_a lambda^0_a w_a (3 e_a + 9 (e_a.u0) e_a - 3 u0).
-template <int D, class S, bool WALLS>
+template <int L, class S, bool WALLS>
 __global__ __launch_bounds__(256) void k_adjoint_init_map(const typename Store<S>::C* __restrict__ lam,
                                                           const double* __restrict__ u0,
                                                           double* __restrict__ u0bar, Dims g,
                                                           int bx_shift)
 {
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     int x, y, z;
     if (!node_of_item(g, bx_shift, x, y, z)) return;
     const unsigned N = g.N;
@@ -202,23 +202,23 @@ __global__ __launch_bounds__(256) void k_adjoint_init_map(const typename Store<S
         for (int d = 0; d < 3; ++d) u0bar[size_t(d) * N + own] = 0.0;
         return;
     }
-    const double u[3] = {u0[own], u0[size_t(N) + own], D == 3 ? u0[2 * size_t(N) + own] : 0.0};
+    const double u[3] = {u0[own], u0[size_t(N) + own], kDim<L> == 3 ? u0[2 * size_t(N) + own] : 0.0};
     double m0 = 0.0, m1[3] = {0.0, 0.0, 0.0}, m2[3] = {0.0, 0.0, 0.0};
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        constexpr auto& L = kLattice<D>;
-        const double wl = L.w[a] * double(lam[slot<Q>(a, own, g.S)]);
-        const double edu = eterm<L.e[a][0]>(u[0]) + eterm<L.e[a][1]>(u[1]) + eterm<L.e[a][2]>(u[2]);
+        constexpr auto& LT = kLattice<L>;
+        const double wl = LT.w[a] * double(lam[slot<Q>(a, own, g.S)]);
+        const double edu = eterm<LT.e[a][0]>(u[0]) + eterm<LT.e[a][1]>(u[1]) + eterm<LT.e[a][2]>(u[2]);
         m0 += wl;
-        m1[0] += eterm<L.e[a][0]>(wl);
-        m1[1] += eterm<L.e[a][1]>(wl);
-        m1[2] += eterm<L.e[a][2]>(wl);
-        m2[0] += eterm<L.e[a][0]>(wl * edu);
-        m2[1] += eterm<L.e[a][1]>(wl * edu);
-        m2[2] += eterm<L.e[a][2]>(wl * edu);
+        m1[0] += eterm<LT.e[a][0]>(wl);
+        m1[1] += eterm<LT.e[a][1]>(wl);
+        m1[2] += eterm<LT.e[a][2]>(wl);
+        m2[0] += eterm<LT.e[a][0]>(wl * edu);
+        m2[1] += eterm<LT.e[a][1]>(wl * edu);
+        m2[2] += eterm<LT.e[a][2]>(wl * edu);
     });
     for (int d = 0; d < 3; ++d)
-        u0bar[size_t(d) * N + own] = d < D ? 3.0 * m1[d] + 9.0 * m2[d] - 3.0 * m0 * u[d] : 0.0;
+        u0bar[size_t(d) * N + own] = d < kDim<L> ? 3.0 * m1[d] + 9.0 * m2[d] - 3.0 * m0 * u[d] : 0.0;
 }
 
 // Sums the per-workgroup slots in workgroup order (one workgroup).

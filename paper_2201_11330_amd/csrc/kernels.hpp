@@ -115,7 +115,16 @@ struct Dims {
     int bc[3];
     unsigned N;  // nx*ny*nz
     int S;       // log2 of the tile length T of the stored state
+    // Per-node link bits when a solid mask is set (else null): bit a is set
+    // when the pull source x - e_a is a wall (solid node or outside the
+    // box), bit 31 when the node itself is solid.
+    const unsigned* links;
 };
+
+__device__ __forceinline__ unsigned node_index(const Dims& g, int x, int y, int z)
+{
+    return unsigned(x) + unsigned(g.nx) * (unsigned(y) + unsigned(g.ny) * unsigned(z));
+}
 
 // Element offset of direction a of node idx in a stored state.
 template <int Q>
@@ -155,11 +164,17 @@ __device__ __forceinline__ Axis3 axis3(int c, int n, int bc)
     return r;
 }
 
-__device__ __forceinline__ bool is_solid(const Dims& g, int x, int y, int z)
+__device__ __forceinline__ bool axis_solid(const Dims& g, int x, int y, int z)
 {
     return (g.bc[0] == kSolidEnds && (x == 0 || x == g.nx - 1)) ||
            (g.bc[1] == kSolidEnds && (y == 0 || y == g.ny - 1)) ||
            (g.bc[2] == kSolidEnds && (z == 0 || z == g.nz - 1));
+}
+
+__device__ __forceinline__ bool is_solid(const Dims& g, int x, int y, int z)
+{
+    if (g.links) return (g.links[node_index(g, x, y, z)] >> 31) != 0u;
+    return axis_solid(g, x, y, z);
 }
 
 // Node of this work-item for the (BX = 1 << bx_shift) x (256 / BX) tiling.
@@ -174,39 +189,48 @@ __device__ __forceinline__ bool node_of_item(const Dims& g, int bx_shift, int& x
 }
 
 // In-plane index of x + sgn*e_a for every a, and whether that node is a wall.
-template <int D, bool WALLS, int SGN>
+template <int L, bool WALLS, int SGN>
 __device__ __forceinline__ void link_nodes(const Dims& g, int x, int y, int z,
-                                           unsigned (&idx)[Lattice<D>::Q],
-                                           bool (&wall)[Lattice<D>::Q])
+                                           unsigned (&idx)[Lattice<L>::Q],
+                                           bool (&wall)[Lattice<L>::Q])
 {
     const Axis3 ax = axis3<WALLS>(x, g.nx, g.bc[0]);
     const Axis3 ay = axis3<WALLS>(y, g.ny, g.bc[1]);
     Axis3 az;
-    if constexpr (D == 3) {
+    if constexpr (kDim<L> == 3) {
         az = axis3<WALLS>(z, g.nz, g.bc[2]);
     } else {
         az = Axis3{{z, z, z}, {false, false, false}};
     }
-    static_for<Lattice<D>::Q>([&](auto ac) {
+    static_for<Lattice<L>::Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        constexpr int kx = 1 + SGN * kLattice<D>.e[a][0];
-        constexpr int ky = 1 + SGN * kLattice<D>.e[a][1];
-        constexpr int kz = 1 + SGN * kLattice<D>.e[a][2];
+        constexpr int kx = 1 + SGN * kLattice<L>.e[a][0];
+        constexpr int ky = 1 + SGN * kLattice<L>.e[a][1];
+        constexpr int kz = 1 + SGN * kLattice<L>.e[a][2];
         idx[a] = unsigned(ax.c[kx]) + unsigned(g.nx) * (unsigned(ay.c[ky]) + unsigned(g.ny) * unsigned(az.c[kz]));
         wall[a] = WALLS && (ax.wall[kx] || ay.wall[ky] || az.wall[kz]);
     });
+    if (WALLS && g.links) {
+        // x + e_a is the pull source of the opposite direction.
+        const unsigned bits = g.links[node_index(g, x, y, z)];
+        static_for<Lattice<L>::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            constexpr int bit = SGN < 0 ? a : Lattice<L>::opp(a);
+            wall[a] = (bits >> bit) & 1u;
+        });
+    }
 }
 
 // Element offset of the slot holding f^n_a(x) in a stored state (GatherMode),
 // given the pull sources of the node.  The same offsets, written instead of
 // read, import a state: the map is a bijection between (node, direction)
 // pairs of fluid nodes and slots.
-template <int D>
+template <int L>
 __device__ __forceinline__ size_t gather_offset(int mode, int a, unsigned own, unsigned src,
                                                 bool wall, int S)
 {
-    constexpr int Q = Lattice<D>::Q;
-    const int abar = Lattice<D>::opp(a);
+    constexpr int Q = Lattice<L>::Q;
+    const int abar = Lattice<L>::opp(a);
     if (mode == kLocal) return slot<Q>(a, own, S);
     if (mode == kPull) return wall ? slot<Q>(abar, own, S) : slot<Q>(a, src, S);
     return wall ? slot<Q>(a, own, S) : slot<Q>(abar, src, S);  // kPullFlip
@@ -263,48 +287,48 @@ struct CollideArgs {
     C k3, k9;  // 3 (1 - omega/2), 9 (1 - omega/2)
 };
 
-template <int D, class C>
+template <int L, class C>
 struct Moments {
     C rho, ux, uy, uz;
 };
 
-template <int D, class C, bool FORCE>
-__device__ __forceinline__ Moments<D, C> node_moments(const C (&f)[Lattice<D>::Q], const C F[3])
+template <int L, class C, bool FORCE>
+__device__ __forceinline__ Moments<L, C> node_moments(const C (&f)[Lattice<L>::Q], const C F[3])
 {
     C rho = C(-0.0), jx = C(-0.0), jy = C(-0.0), jz = C(-0.0);
-    static_for<Lattice<D>::Q>([&](auto ac) {
+    static_for<Lattice<L>::Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         rho += f[a];
-        jx += eterm<kLattice<D>.e[a][0]>(f[a]);
-        jy += eterm<kLattice<D>.e[a][1]>(f[a]);
-        if constexpr (D == 3) jz += eterm<kLattice<D>.e[a][2]>(f[a]);
+        jx += eterm<kLattice<L>.e[a][0]>(f[a]);
+        jy += eterm<kLattice<L>.e[a][1]>(f[a]);
+        if constexpr (kDim<L> == 3) jz += eterm<kLattice<L>.e[a][2]>(f[a]);
     });
-    Moments<D, C> m;
+    Moments<L, C> m;
     m.rho = rho;
     if constexpr (FORCE) {
         m.ux = jx + C(0.5) * F[0];
         m.uy = jy + C(0.5) * F[1];
-        m.uz = D == 3 ? jz + C(0.5) * F[2] : C(0);
+        m.uz = kDim<L> == 3 ? jz + C(0.5) * F[2] : C(0);
     } else {
         m.ux = jx;
         m.uy = jy;
-        m.uz = D == 3 ? jz : C(0);
+        m.uz = kDim<L> == 3 ? jz : C(0);
     }
     return m;
 }
 
-template <int D, class C, bool FORCE>
-__device__ __forceinline__ void collide(C (&f)[Lattice<D>::Q], const CollideArgs<C>& p)
+template <int L, class C, bool FORCE>
+__device__ __forceinline__ void collide(C (&f)[Lattice<L>::Q], const CollideArgs<C>& p)
 {
-    const Moments<D, C> m = node_moments<D, C, FORCE>(f, p.F);
-    const C usq = m.ux * m.ux + m.uy * m.uy + (D == 3 ? m.uz * m.uz : C(0));
+    const Moments<L, C> m = node_moments<L, C, FORCE>(f, p.F);
+    const C usq = m.ux * m.ux + m.uy * m.uy + (kDim<L> == 3 ? m.uz * m.uz : C(0));
     const C base = m.rho - C(1.5) * usq;
     C uF = C(0);
-    if constexpr (FORCE) uF = m.ux * p.F[0] + m.uy * p.F[1] + (D == 3 ? m.uz * p.F[2] : C(0));
-    static_for<Lattice<D>::Q>([&](auto ac) {
+    if constexpr (FORCE) uF = m.ux * p.F[0] + m.uy * p.F[1] + (kDim<L> == 3 ? m.uz * p.F[2] : C(0));
+    static_for<Lattice<L>::Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        constexpr int ex = kLattice<D>.e[a][0], ey = kLattice<D>.e[a][1], ez = kLattice<D>.e[a][2];
-        const C w = C(kLattice<D>.w[a]);
+        constexpr int ex = kLattice<L>.e[a][0], ey = kLattice<L>.e[a][1], ez = kLattice<L>.e[a][2];
+        const C w = C(kLattice<L>.w[a]);
         const C edu = eterm<ex>(m.ux) + eterm<ey>(m.uy) + eterm<ez>(m.uz);
         const C feq = w * (base + edu * (C(3) + C(4.5) * edu));
         C fs = f[a] + p.omega * (feq - f[a]);
@@ -327,12 +351,12 @@ struct StepArgs {
 };
 
 // Fused pull-stream + bounce-back + collide (AB).
-template <int D, class S, bool WALLS, bool FORCE, bool NT>
+template <int L, class S, bool WALLS, bool FORCE, bool NT>
 __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restrict__ dst,
                                                  StepArgs<typename Store<S>::C> p)
 {
     using C = typename Store<S>::C;
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     if (WALLS && is_solid(p.g, x, y, z)) return;
@@ -340,16 +364,16 @@ __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restri
     const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
     unsigned idx[Q];
     bool wall[Q];
-    link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
+    link_nodes<L, WALLS, -1>(p.g, x, y, z, idx, wall);
     C f[Q];
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        constexpr int abar = Lattice<D>::opp(a);
-        constexpr bool aligned = kLattice<D>.e[a][0] == 0;
+        constexpr int abar = Lattice<L>::opp(a);
+        constexpr bool aligned = kLattice<L>.e[a][0] == 0;
         const S* ptr = src + ((WALLS && wall[a]) ? slot<Q>(abar, own, TS) : slot<Q>(a, idx[a], TS));
         f[a] = Store<S>::load(get<NT && aligned>(ptr));
     });
-    collide<D, C, FORCE>(f, p.c);
+    collide<L, C, FORCE>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         put<NT>(dst + slot<Q>(a, own, TS), Store<S>::save(f[a]));
@@ -357,12 +381,12 @@ __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restri
 }
 
 // AA even step: own slots in, opposite own slots out.
-template <int D, class S, bool WALLS, bool FORCE, bool NT>
+template <int L, class S, bool WALLS, bool FORCE, bool NT>
 __global__ LBM_STEP_BOUNDS void k_step_aa_even(S* __restrict__ A,
                                                       StepArgs<typename Store<S>::C> p)
 {
     using C = typename Store<S>::C;
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     if (WALLS && is_solid(p.g, x, y, z)) return;
@@ -373,22 +397,22 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_even(S* __restrict__ A,
         constexpr int a = decltype(ac)::value;
         f[a] = Store<S>::load(get<NT>(A + slot<Q>(a, own, TS)));
     });
-    collide<D, C, FORCE>(f, p.c);
+    collide<L, C, FORCE>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        put<NT>(A + slot<Q>(Lattice<D>::opp(a), own, TS), Store<S>::save(f[a]));
+        put<NT>(A + slot<Q>(Lattice<L>::opp(a), own, TS), Store<S>::save(f[a]));
     });
 }
 
 // AA odd step: f_a(x) from slot abar of x - e_a (or slot a of x at a wall);
 // f*_a(x) goes to slot a of x + e_a (or slot abar of x at a wall), which is
 // the address read for direction abar.
-template <int D, class S, bool WALLS, bool FORCE, bool NT>
+template <int L, class S, bool WALLS, bool FORCE, bool NT>
 __global__ LBM_STEP_BOUNDS void k_step_aa_odd(S* __restrict__ A,
                                                      StepArgs<typename Store<S>::C> p)
 {
     using C = typename Store<S>::C;
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     if (WALLS && is_solid(p.g, x, y, z)) return;
@@ -396,22 +420,22 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_odd(S* __restrict__ A,
     const unsigned own = unsigned(x) + unsigned(p.g.nx) * (unsigned(y) + unsigned(p.g.ny) * unsigned(z));
     unsigned idx[Q];
     bool wall[Q];
-    link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
+    link_nodes<L, WALLS, -1>(p.g, x, y, z, idx, wall);
     size_t off[Q];
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        constexpr int abar = Lattice<D>::opp(a);
+        constexpr int abar = Lattice<L>::opp(a);
         off[a] = (WALLS && wall[a]) ? slot<Q>(a, own, TS) : slot<Q>(abar, idx[a], TS);
     });
     C f[Q];
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        f[a] = Store<S>::load(get<NT && kLattice<D>.e[a][0] == 0>(A + off[a]));
+        f[a] = Store<S>::load(get<NT && kLattice<L>.e[a][0] == 0>(A + off[a]));
     });
-    collide<D, C, FORCE>(f, p.c);
+    collide<L, C, FORCE>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        put<NT>(A + off[Lattice<D>::opp(a)], Store<S>::save(f[a]));
+        put<NT>(A + off[Lattice<L>::opp(a)], Store<S>::save(f[a]));
     });
 }
 
@@ -429,13 +453,13 @@ struct IoArgs {
 
 // f^n from equilibrium (rho, u) plus optional noise, or from f (when f is
 // non-null), written into the stored state.  Deviation storages store f - w.
-template <int D, class S, bool WALLS>
+template <int L, class S, bool WALLS>
 __global__ __launch_bounds__(256) void k_import(S* __restrict__ A, const double* __restrict__ f,
                                                 const double* __restrict__ rho,
                                                 const double* __restrict__ u,
                                                 const double* __restrict__ noise, IoArgs p)
 {
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     const unsigned N = p.g.N;
@@ -443,7 +467,7 @@ __global__ __launch_bounds__(256) void k_import(S* __restrict__ A, const double*
     if (WALLS && is_solid(p.g, x, y, z)) return;
     unsigned idx[Q];
     bool wall[Q];
-    link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
+    link_nodes<L, WALLS, -1>(p.g, x, y, z, idx, wall);
     double fn[Q];
     if (f) {
         static_for<Q>([&](auto ac) {
@@ -452,13 +476,13 @@ __global__ __launch_bounds__(256) void k_import(S* __restrict__ A, const double*
         });
     } else {
         const double r = rho[own];
-        const double ux = u[own], uy = u[size_t(N) + own], uz = D == 3 ? u[2 * size_t(N) + own] : 0.0;
+        const double ux = u[own], uy = u[size_t(N) + own], uz = kDim<L> == 3 ? u[2 * size_t(N) + own] : 0.0;
         const double usq = ux * ux + uy * uy + uz * uz;
         static_for<Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            constexpr auto& L = kLattice<D>;
-            const double edu = eterm<L.e[a][0]>(ux) + eterm<L.e[a][1]>(uy) + eterm<L.e[a][2]>(uz);
-            double v = L.w[a] * (r + (3.0 * edu + 4.5 * edu * edu - 1.5 * usq));
+            constexpr auto& LT = kLattice<L>;
+            const double edu = eterm<LT.e[a][0]>(ux) + eterm<LT.e[a][1]>(uy) + eterm<LT.e[a][2]>(uz);
+            double v = LT.w[a] * (r + (3.0 * edu + 4.5 * edu * edu - 1.5 * usq));
             if (noise) v += noise[size_t(a) * N + own];
             fn[a] = v;
         });
@@ -466,33 +490,33 @@ __global__ __launch_bounds__(256) void k_import(S* __restrict__ A, const double*
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         double v = fn[a];
-        if constexpr (Store<S>::kDeviation) v -= kLattice<D>.w[a];
-        A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.S)] =
+        if constexpr (Store<S>::kDeviation) v -= kLattice<L>.w[a];
+        A[gather_offset<L>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.S)] =
             Store<S>::save(typename Store<S>::C(v));
     });
 }
 
 // Gathers f^n (in the storage's arithmetic type, as stored: f or f - w).
-template <int D, class S, bool WALLS>
+template <int L, class S, bool WALLS>
 __device__ __forceinline__ void gather_node(const S* __restrict__ A, const IoArgs& p, int x, int y,
                                             int z, unsigned own,
-                                            typename Store<S>::C (&f)[Lattice<D>::Q])
+                                            typename Store<S>::C (&f)[Lattice<L>::Q])
 {
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     unsigned idx[Q];
     bool wall[Q];
-    link_nodes<D, WALLS, -1>(p.g, x, y, z, idx, wall);
+    link_nodes<L, WALLS, -1>(p.g, x, y, z, idx, wall);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        f[a] = Store<S>::load(A[gather_offset<D>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.S)]);
+        f[a] = Store<S>::load(A[gather_offset<L>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.S)]);
     });
 }
 
-template <int D, class S, bool WALLS>
+template <int L, class S, bool WALLS>
 __global__ __launch_bounds__(256) void k_export(const S* __restrict__ A, double* __restrict__ f,
                                                 IoArgs p)
 {
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     const unsigned N = p.g.N;
@@ -502,23 +526,23 @@ __global__ __launch_bounds__(256) void k_export(const S* __restrict__ A, double*
         return;
     }
     typename Store<S>::C fn[Q];
-    gather_node<D, S, WALLS>(A, p, x, y, z, own, fn);
+    gather_node<L, S, WALLS>(A, p, x, y, z, own, fn);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         double v = double(fn[a]);
-        if constexpr (Store<S>::kDeviation) v += kLattice<D>.w[a];
+        if constexpr (Store<S>::kDeviation) v += kLattice<L>.w[a];
         f[size_t(a) * N + own] = v;
     });
 }
 
 // PostProcessing: rho = sum f (= 1 + sum (f - w) for deviation storage),
 // u = sum e f + F/2.
-template <int D, class S, bool WALLS, class O>
+template <int L, class S, bool WALLS, class O>
 __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ A, O* __restrict__ rho,
                                                  O* __restrict__ u, IoArgs p)
 {
     using C = typename Store<S>::C;
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     int x, y, z;
     if (!node_of_item(p.g, p.bx_shift, x, y, z)) return;
     const unsigned N = p.g.N;
@@ -529,9 +553,9 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ A, O* __r
         return;
     }
     C fn[Q];
-    gather_node<D, S, WALLS>(A, p, x, y, z, own, fn);
+    gather_node<L, S, WALLS>(A, p, x, y, z, own, fn);
     const C F[3] = {C(p.F[0]), C(p.F[1]), C(p.F[2])};
-    const Moments<D, C> m = node_moments<D, C, true>(fn, F);
+    const Moments<L, C> m = node_moments<L, C, true>(fn, F);
     if (rho) rho[own] = O(Store<S>::kDeviation ? 1.0 + double(m.rho) : double(m.rho));
     if (u) {
         u[own] = O(m.ux);
@@ -546,13 +570,13 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ A, O* __r
 constexpr int kReduceThreads = 256;
 constexpr int kReduceBlocks = 1024;
 
-template <int D, class S, bool WALLS>
+template <int L, class S, bool WALLS>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const S* __restrict__ A,
                                                                     double* __restrict__ partials,
                                                                     IoArgs p)
 {
     using C = typename Store<S>::C;
-    constexpr int Q = Lattice<D>::Q;
+    constexpr int Q = Lattice<L>::Q;
     __shared__ double s_mass[kReduceThreads], s_ke[kReduceThreads], s_max[kReduceThreads],
         s_bad[kReduceThreads], s_cnt[kReduceThreads];
     double mass = 0.0, ke = 0.0, umax = 0.0, bad = 0.0, cnt = 0.0;
@@ -566,10 +590,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const S* __r
         const int z = int(yz / unsigned(p.g.ny));
         if (WALLS && is_solid(p.g, x, y, z)) continue;
         C fn[Q];
-        gather_node<D, S, WALLS>(A, p, x, y, z, n, fn);
+        gather_node<L, S, WALLS>(A, p, x, y, z, n, fn);
         for (int a = 0; a < Q; ++a)
             if (!isfinite(double(fn[a]))) bad += 1.0;
-        const Moments<D, C> m = node_moments<D, C, true>(fn, F);
+        const Moments<L, C> m = node_moments<L, C, true>(fn, F);
         const double ux = m.ux, uy = m.uy, uz = m.uz;
         const double u2 = ux * ux + uy * uy + uz * uz;
         mass += double(m.rho);
@@ -639,6 +663,111 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* _
         out[1] = 0.5 * s[1][0];
         out[2] = s[2][0];
         out[3] = s[3][0];
+    }
+}
+
+// Sums slots 0..2 of the block partials in block order (one workgroup).
+__global__ __launch_bounds__(kReduceThreads) void k_sum3(const double* __restrict__ partials,
+                                                         int nblocks, double* __restrict__ out)
+{
+    __shared__ double s[3][kReduceThreads];
+    const int t = threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = t; b < nblocks; b += kReduceThreads)
+        for (int d = 0; d < 3; ++d) v[d] += partials[5 * size_t(b) + d];
+    for (int d = 0; d < 3; ++d) s[d][t] = v[d];
+    __syncthreads();
+    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int d = 0; d < 3; ++d) s[d][t] += s[d][t + h];
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int d = 0; d < 3; ++d) out[d] = s[d][0];
+}
+
+// ---------------------------------------------------------------------------
+// Solid mask (SetGeometry with a user geo array) and wall force.
+
+// Link bits of every node from a solid mask (nonzero = solid) and the axis
+// boundaries; g.links must be null here.
+template <int L>
+__global__ __launch_bounds__(256) void k_build_links(const unsigned char* __restrict__ mask,
+                                                     unsigned* __restrict__ links, Dims g,
+                                                     int bx_shift)
+{
+    constexpr int Q = Lattice<L>::Q;
+    int x, y, z;
+    if (!node_of_item(g, bx_shift, x, y, z)) return;
+    const unsigned own = node_index(g, x, y, z);
+    unsigned idx[Q];
+    bool wall[Q];
+    link_nodes<L, true, -1>(g, x, y, z, idx, wall);
+    unsigned bits = (axis_solid(g, x, y, z) || mask[own]) ? (1u << 31) : 0u;
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        if (wall[a] || mask[idx[a]]) bits |= 1u << a;
+    });
+    links[own] = bits;
+}
+
+// Momentum exchanged with the walls in the last propagation (the drag
+// evaluation of Sec. 4): for each fluid node x and direction a whose
+// neighbour x + e_a is a wall, the population that left along a came back
+// as f^n_abar(x), so the wall received 2 f^n_abar(x) e_a.  Per-block FP64
+// partials over a fixed grid-stride assignment (slots 0..2 of 5).
+template <int L, class S>
+__global__ __launch_bounds__(kReduceThreads) void k_wall_force(const S* __restrict__ A,
+                                                               double* __restrict__ partials,
+                                                               IoArgs p)
+{
+    using C = typename Store<S>::C;
+    constexpr int Q = Lattice<L>::Q;
+    __shared__ double s[3][kReduceThreads];
+    double F[3] = {0.0, 0.0, 0.0};
+    const unsigned N = p.g.N;
+    for (unsigned n = blockIdx.x * kReduceThreads + threadIdx.x; n < N;
+         n += kReduceBlocks * kReduceThreads) {
+        const int x = int(n % unsigned(p.g.nx));
+        const unsigned yz = n / unsigned(p.g.nx);
+        const int y = int(yz % unsigned(p.g.ny));
+        const int z = int(yz / unsigned(p.g.ny));
+        if (is_solid(p.g, x, y, z)) continue;
+        unsigned idx[Q];
+        bool out[Q];
+        link_nodes<L, true, +1>(p.g, x, y, z, idx, out);
+        bool any = false;
+        for (int a = 0; a < Q; ++a) any = any || out[a];
+        if (!any) continue;
+        C fn[Q];
+        gather_node<L, S, true>(A, p, x, y, z, n, fn);
+        static_for<Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            constexpr int abar = Lattice<L>::opp(a);
+            if (out[a]) {
+                double f = double(fn[abar]);
+                if constexpr (Store<S>::kDeviation) f += kLattice<L>.w[abar];
+                F[0] += eterm<kLattice<L>.e[a][0]>(2.0 * f);
+                F[1] += eterm<kLattice<L>.e[a][1]>(2.0 * f);
+                F[2] += eterm<kLattice<L>.e[a][2]>(2.0 * f);
+            }
+        });
+    }
+    const int t = threadIdx.x;
+    for (int d = 0; d < 3; ++d) s[d][t] = F[d];
+    __syncthreads();
+    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int d = 0; d < 3; ++d) s[d][t] += s[d][t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double* o = partials + 5 * size_t(blockIdx.x);
+        o[0] = s[0][0];
+        o[1] = s[1][0];
+        o[2] = s[2][0];
+        o[3] = 0.0;
+        o[4] = 0.0;
     }
 }
 

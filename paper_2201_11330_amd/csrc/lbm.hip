@@ -91,6 +91,7 @@ struct lbm_ctx {
     bool state_valid = false;
     long long steps = 0;
 
+    unsigned* links = nullptr;     // per-node link bits of a solid mask (lbm_set_solid)
     double* d_partials = nullptr;  // kReduceBlocks * 5 + 4 doubles
     double* h_result = nullptr;    // 4 doubles, pinned
 
@@ -128,6 +129,7 @@ Dims dims_of(const lbm_ctx* c)
     for (int d = 0; d < 3; ++d) g.bc[d] = c->bc[d];
     g.N = c->N;
     g.S = c->S;
+    g.links = c->links;
     return g;
 }
 
@@ -175,22 +177,22 @@ struct WorkspaceLayout {
 WorkspaceLayout workspace_layout(const lbm_ctx* c, int k);
 
 // Kernel instantiations of one lattice and storage.
-template <int D, class S>
+template <int L, class S>
 struct Impl {
     template <bool W, bool F>
     static void step_ab(lbm_ctx* c, const S* src, S* dst)
     {
-        hipLaunchKernelGGL((k_step_ab<D, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, src, dst,
+        hipLaunchKernelGGL((k_step_ab<L, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, src, dst,
                            step_args<typename Store<S>::C>(c));
     }
     template <bool W, bool F>
     static void step_aa(lbm_ctx* c, S* A, bool odd)
     {
         if (odd)
-            hipLaunchKernelGGL((k_step_aa_odd<D, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, A,
+            hipLaunchKernelGGL((k_step_aa_odd<L, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, A,
                                step_args<typename Store<S>::C>(c));
         else
-            hipLaunchKernelGGL((k_step_aa_even<D, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, A,
+            hipLaunchKernelGGL((k_step_aa_even<L, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, A,
                                step_args<typename Store<S>::C>(c));
     }
 
@@ -200,22 +202,32 @@ struct Impl {
     static lbm_status capture(lbm_ctx* c)
     {
         if (!c->capture_stream) LBM_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         hipStream_t saved_stream = c->stream;
         const int saved_cur = c->cur;
         const long long saved_steps = c->steps;
         c->stream = c->capture_stream;
         c->cur = 0;
         c->steps = 0;
-        LBM_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-        eager(c, kGraphSteps);
+        const lbm_status st = eager(c, kGraphSteps);
         hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+        e = hipStreamEndCapture(c->capture_stream, &g);
         c->stream = saved_stream;
         c->cur = saved_cur;
         c->steps = saved_steps;
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        if (st != LBM_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != LBM_OK ? st : hip_fail(e, "hipStreamEndCapture");
+        }
         c->graph = g;
-        LBM_HIP(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+        e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(c->graph);
+            c->graph = nullptr;
+            c->graph_exec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
         return LBM_OK;
     }
 
@@ -288,7 +300,7 @@ struct Impl {
     template <bool W, bool F>
     static void adj_step(lbm_ctx* c, const S* g, const C* lin, C* lout, double* acc)
     {
-        hipLaunchKernelGGL((k_adjoint_step<D, S, W, F>), c->grid, c->block, 0, c->stream, g, lin, lout,
+        hipLaunchKernelGGL((k_adjoint_step<L, S, W, F>), c->grid, c->block, 0, c->stream, g, lin, lout,
                            acc, adj_args(c));
     }
 
@@ -298,26 +310,26 @@ struct Impl {
     static lbm_status adjoint(lbm_ctx* c, int n, int k, const void* ckpt, void* ws,
                               const double* u0, const double* ubar, double* u0bar, double* out4)
     {
-        const WorkspaceLayout L = workspace_layout(c, k);
+        const WorkspaceLayout W = workspace_layout(c, k);
         char* w = static_cast<char*>(ws);
-        C* lam[2] = {reinterpret_cast<C*>(w + L.lam0), reinterpret_cast<C*>(w + L.lam1)};
-        double* acc = reinterpret_cast<double*>(w + L.acc);
-        double* result = reinterpret_cast<double*>(w + L.result);
+        C* lam[2] = {reinterpret_cast<C*>(w + W.lam0), reinterpret_cast<C*>(w + W.lam1)};
+        double* acc = reinterpret_cast<double*>(w + W.acc);
+        double* result = reinterpret_cast<double*>(w + W.result);
         const Dims g = dims_of(c);
-        hipLaunchKernelGGL(k_fill_zero, dim3((L.acc_doubles + 255) / 256), dim3(256), 0, c->stream, acc,
-                           L.acc_doubles);
+        hipLaunchKernelGGL(k_fill_zero, dim3((W.acc_doubles + 255) / 256), dim3(256), 0, c->stream, acc,
+                           W.acc_doubles);
         if (c->walls)
-            hipLaunchKernelGGL((k_adjoint_seed<D, S, true>), c->grid, c->block, 0, c->stream, ubar, lam[0],
+            hipLaunchKernelGGL((k_adjoint_seed<L, S, true>), c->grid, c->block, 0, c->stream, ubar, lam[0],
                                acc, g, c->bx_shift);
         else
-            hipLaunchKernelGGL((k_adjoint_seed<D, S, false>), c->grid, c->block, 0, c->stream, ubar, lam[0],
+            hipLaunchKernelGGL((k_adjoint_seed<L, S, false>), c->grid, c->block, 0, c->stream, ubar, lam[0],
                                acc, g, c->bx_shift);
         int cur = 0;
         const char* ck = static_cast<const char*>(ckpt);
         for (int s = n / k - 1; s >= 0; --s) {
-            const S* state0 = reinterpret_cast<const S*>(ck + size_t(s) * L.state_bytes);
+            const S* state0 = reinterpret_cast<const S*>(ck + size_t(s) * W.state_bytes);
             auto state = [&](int j) -> const S* {
-                return j == 0 ? state0 : reinterpret_cast<const S*>(w + L.seg + size_t(j - 1) * L.state_bytes);
+                return j == 0 ? state0 : reinterpret_cast<const S*>(w + W.seg + size_t(j - 1) * W.state_bytes);
             };
             for (int j = 1; j < k; ++j)
                 step_between(c, state(j - 1), const_cast<S*>(state(j)));
@@ -332,15 +344,37 @@ struct Impl {
             }
         }
         if (c->walls)
-            hipLaunchKernelGGL((k_adjoint_init_map<D, S, true>), c->grid, c->block, 0, c->stream, lam[cur], u0,
+            hipLaunchKernelGGL((k_adjoint_init_map<L, S, true>), c->grid, c->block, 0, c->stream, lam[cur], u0,
                                u0bar, g, c->bx_shift);
         else
-            hipLaunchKernelGGL((k_adjoint_init_map<D, S, false>), c->grid, c->block, 0, c->stream, lam[cur], u0,
+            hipLaunchKernelGGL((k_adjoint_init_map<L, S, false>), c->grid, c->block, 0, c->stream, lam[cur], u0,
                                u0bar, g, c->bx_shift);
-        hipLaunchKernelGGL(k_adjoint_sum, dim3(1), dim3(256), 0, c->stream, acc, L.nblocks, result);
+        hipLaunchKernelGGL(k_adjoint_sum, dim3(1), dim3(256), 0, c->stream, acc, W.nblocks, result);
         LBM_HIP(hipGetLastError());
         LBM_HIP(hipMemcpyAsync(out4, result, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         LBM_HIP(hipStreamSynchronize(c->stream));
+        return LBM_OK;
+    }
+
+    static lbm_status build_links(lbm_ctx* c, const unsigned char* mask)
+    {
+        Dims g = dims_of(c);
+        g.links = nullptr;
+        hipLaunchKernelGGL((k_build_links<L>), c->grid, c->block, 0, c->stream, mask, c->links, g,
+                           c->bx_shift);
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    static lbm_status wall_force(lbm_ctx* c)
+    {
+        IoArgs p = io_args(c);
+        const S* A = static_cast<const S*>(c->buf[c->cur]);
+        hipLaunchKernelGGL((k_wall_force<L, S>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, c->stream,
+                           A, c->d_partials, p);
+        hipLaunchKernelGGL(k_sum3, dim3(1), dim3(kReduceThreads), 0, c->stream, c->d_partials,
+                           kReduceBlocks, c->d_partials + 5 * size_t(kReduceBlocks));
+        LBM_HIP(hipGetLastError());
         return LBM_OK;
     }
 
@@ -350,10 +384,10 @@ struct Impl {
         IoArgs p = io_args(c);
         S* A = static_cast<S*>(c->buf[c->cur]);
         if (c->walls)
-            hipLaunchKernelGGL((k_import<D, S, true>), c->grid, c->block, 0, c->stream, A, f, rho, u,
+            hipLaunchKernelGGL((k_import<L, S, true>), c->grid, c->block, 0, c->stream, A, f, rho, u,
                                noise, p);
         else
-            hipLaunchKernelGGL((k_import<D, S, false>), c->grid, c->block, 0, c->stream, A, f, rho, u,
+            hipLaunchKernelGGL((k_import<L, S, false>), c->grid, c->block, 0, c->stream, A, f, rho, u,
                                noise, p);
         LBM_HIP(hipGetLastError());
         return LBM_OK;
@@ -364,9 +398,9 @@ struct Impl {
         IoArgs p = io_args(c);
         const S* A = static_cast<const S*>(c->buf[c->cur]);
         if (c->walls)
-            hipLaunchKernelGGL((k_export<D, S, true>), c->grid, c->block, 0, c->stream, A, f, p);
+            hipLaunchKernelGGL((k_export<L, S, true>), c->grid, c->block, 0, c->stream, A, f, p);
         else
-            hipLaunchKernelGGL((k_export<D, S, false>), c->grid, c->block, 0, c->stream, A, f, p);
+            hipLaunchKernelGGL((k_export<L, S, false>), c->grid, c->block, 0, c->stream, A, f, p);
         LBM_HIP(hipGetLastError());
         return LBM_OK;
     }
@@ -377,10 +411,10 @@ struct Impl {
         IoArgs p = io_args(c);
         const S* A = static_cast<const S*>(c->buf[c->cur]);
         if (c->walls)
-            hipLaunchKernelGGL((k_moments<D, S, true, O>), c->grid, c->block, 0, c->stream, A, rho, u,
+            hipLaunchKernelGGL((k_moments<L, S, true, O>), c->grid, c->block, 0, c->stream, A, rho, u,
                                p);
         else
-            hipLaunchKernelGGL((k_moments<D, S, false, O>), c->grid, c->block, 0, c->stream, A, rho,
+            hipLaunchKernelGGL((k_moments<L, S, false, O>), c->grid, c->block, 0, c->stream, A, rho,
                                u, p);
     }
 
@@ -399,10 +433,10 @@ struct Impl {
         IoArgs p = io_args(c);
         const S* A = static_cast<const S*>(c->buf[c->cur]);
         if (c->walls)
-            hipLaunchKernelGGL((k_reduce_partials<D, S, true>), dim3(kReduceBlocks),
+            hipLaunchKernelGGL((k_reduce_partials<L, S, true>), dim3(kReduceBlocks),
                                dim3(kReduceThreads), 0, c->stream, A, c->d_partials, p);
         else
-            hipLaunchKernelGGL((k_reduce_partials<D, S, false>), dim3(kReduceBlocks),
+            hipLaunchKernelGGL((k_reduce_partials<L, S, false>), dim3(kReduceBlocks),
                                dim3(kReduceThreads), 0, c->stream, A, c->d_partials, p);
         hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, c->stream, c->d_partials,
                            kReduceBlocks, int(Store<S>::kDeviation),
@@ -412,25 +446,22 @@ struct Impl {
     }
 };
 
-// Calls Impl<D, S>::fn(c, args...) for the context's lattice and storage.
-#define LBM_DISPATCH(c, CALL)                                                    \
-    do {                                                                         \
-        if ((c)->D == 2) {                                                       \
-            switch ((c)->storage) {                                              \
-            case LBM_F64: { using I = Impl<2, double>; return I::CALL; }         \
-            case LBM_F32: { using I = Impl<2, float>; return I::CALL; }          \
-            case LBM_F16_DEV: { using I = Impl<2, __half>; return I::CALL; }     \
-            case LBM_BF16_DEV: { using I = Impl<2, __hip_bfloat16>; return I::CALL; } \
-            }                                                                    \
-        } else {                                                                 \
-            switch ((c)->storage) {                                              \
-            case LBM_F64: { using I = Impl<3, double>; return I::CALL; }         \
-            case LBM_F32: { using I = Impl<3, float>; return I::CALL; }          \
-            case LBM_F16_DEV: { using I = Impl<3, __half>; return I::CALL; }     \
-            case LBM_BF16_DEV: { using I = Impl<3, __hip_bfloat16>; return I::CALL; } \
-            }                                                                    \
-        }                                                                        \
-        return fail(LBM_EINVAL, "unknown lattice/storage");                      \
+// Calls Impl<L, S>::fn(c, args...) for the context's lattice and storage.
+#define LBM_DISPATCH_STORAGE(c, LK, CALL)                                            \
+    switch ((c)->storage) {                                                          \
+    case LBM_F64: { using I = Impl<LK, double>; return I::CALL; }                    \
+    case LBM_F32: { using I = Impl<LK, float>; return I::CALL; }                     \
+    case LBM_F16_DEV: { using I = Impl<LK, __half>; return I::CALL; }                \
+    case LBM_BF16_DEV: { using I = Impl<LK, __hip_bfloat16>; return I::CALL; }       \
+    }
+#define LBM_DISPATCH(c, CALL)                                                        \
+    do {                                                                             \
+        switch ((c)->lattice) {                                                      \
+        case LBM_D2Q9: LBM_DISPATCH_STORAGE(c, 0, CALL) break;                       \
+        case LBM_D3Q19: LBM_DISPATCH_STORAGE(c, 1, CALL) break;                      \
+        case LBM_D3Q27: LBM_DISPATCH_STORAGE(c, 2, CALL) break;                      \
+        }                                                                            \
+        return fail(LBM_EINVAL, "unknown lattice/storage");                          \
     } while (0)
 
 lbm_status need_bound(const lbm_ctx* c)
@@ -500,6 +531,16 @@ lbm_status reduce_launch(lbm_ctx* c)
     LBM_DISPATCH(c, reduce(c));
 }
 
+lbm_status build_links_any(lbm_ctx* c, const unsigned char* mask)
+{
+    LBM_DISPATCH(c, build_links(c, mask));
+}
+
+lbm_status wall_force_any(lbm_ctx* c)
+{
+    LBM_DISPATCH(c, wall_force(c));
+}
+
 }  // namespace
 
 extern "C" {
@@ -509,7 +550,8 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
 {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     *out = nullptr;
-    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(LBM_EINVAL, "unknown lattice %d", int(lattice));
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19 && lattice != LBM_D3Q27)
+        return fail(LBM_EINVAL, "unknown lattice %d", int(lattice));
     if (storage_size(storage) == 0) return fail(LBM_EINVAL, "unknown storage %d", int(storage));
     if (flags & ~unsigned(LBM_FLAG_AA | LBM_FLAG_GRAPH)) return fail(LBM_EINVAL, "unknown flags 0x%x", flags);
     const int n[3] = {nx, ny, nz};
@@ -539,7 +581,7 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
     if (!c) return fail(LBM_EINVAL, "out of host memory");
     c->lattice = lattice;
     c->D = lattice == LBM_D2Q9 ? 2 : 3;
-    c->Q = lattice == LBM_D2Q9 ? 9 : 19;
+    c->Q = lattice == LBM_D2Q9 ? 9 : (lattice == LBM_D3Q19 ? 19 : 27);
     c->nx = nx;
     c->ny = ny;
     c->nz = nz;
@@ -675,6 +717,31 @@ lbm_status lbm_reduce(lbm_ctx* c, double* mass, double* kinetic_energy, double* 
 
 long long lbm_steps_taken(const lbm_ctx* c) { return c ? c->steps : -1; }
 
+lbm_status lbm_set_solid(lbm_ctx* c, const unsigned char* solid)
+{
+    lbm_status st = need_bound(c);
+    if (st) return st;
+    if ((st = check_device_ptr(solid, "solid", false))) return st;
+    if (c->graph_exec) return fail(LBM_ESTATE, "lbm_set_solid after a graph was captured");
+    if (!c->links) LBM_HIP(hipMalloc(&c->links, sizeof(unsigned) * size_t(c->N)));
+    c->walls = true;
+    c->state_valid = false;
+    return build_links_any(c, solid);
+}
+
+lbm_status lbm_wall_force(lbm_ctx* c, double force[3])
+{
+    lbm_status st = need_state(c);
+    if (st) return st;
+    if (!force) return fail(LBM_EINVAL, "force is NULL");
+    if ((st = wall_force_any(c))) return st;
+    LBM_HIP(hipMemcpyAsync(c->h_result, c->d_partials + 5 * size_t(kReduceBlocks), 3 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    for (int d = 0; d < 3; ++d) force[d] = c->h_result[d];
+    return LBM_OK;
+}
+
 lbm_status lbm_forward_record(lbm_ctx* c, int n, int k, void* ckpt)
 {
     lbm_status st = need_state(c);
@@ -734,6 +801,7 @@ lbm_status lbm_destroy(lbm_ctx* c)
         hipError_t e = hipHostFree(c->h_result);
         if (e != hipSuccess) st = hip_fail(e, "hipHostFree");
     }
+    if (c->links) (void)hipFree(c->links);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);

@@ -16,20 +16,20 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
 # Enumerations of lbm.h.
-D2Q9, D3Q19 = 0, 1
+D2Q9, D3Q19, D3Q27 = 0, 1, 2
 PERIODIC, SOLID_ENDS, WALLS_OUTSIDE = 0, 1, 2
 F64, F32, F16_DEV, BF16_DEV = 0, 1, 2, 3
 FLAG_AA, FLAG_GRAPH = 1, 2
 OK, EINVAL, ENOTBOUND, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 
 STORAGE_NAMES = {"f64": F64, "f32": F32, "f16": F16_DEV, "bf16": BF16_DEV}
-Q_OF = {D2Q9: 9, D3Q19: 19}
+Q_OF = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 
 # Every symbol include/lbm.h declares.
 EXPORTS = (
     "lbm_create", "lbm_buffer_bytes", "lbm_bind", "lbm_init_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments", "lbm_reduce",
-    "lbm_steps_taken", "lbm_forward_record", "lbm_adjoint_workspace_bytes", "lbm_adjoint",
+    "lbm_steps_taken", "lbm_set_solid", "lbm_wall_force", "lbm_forward_record", "lbm_adjoint_workspace_bytes", "lbm_adjoint",
     "lbm_destroy", "lbm_status_string", "lbm_last_error",
 )
 
@@ -80,6 +80,10 @@ def lib():
     L.lbm_reduce.restype = st
     L.lbm_steps_taken.argtypes = [vp]
     L.lbm_steps_taken.restype = ctypes.c_longlong
+    L.lbm_set_solid.argtypes = [vp, vp]
+    L.lbm_set_solid.restype = st
+    L.lbm_wall_force.argtypes = [vp, dp]
+    L.lbm_wall_force.restype = st
     L.lbm_forward_record.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
     L.lbm_forward_record.restype = st
     L.lbm_adjoint_workspace_bytes.argtypes = [vp, ctypes.c_int]
@@ -207,6 +211,21 @@ class LBM:
         check(lib().lbm_moments(self._h, _ptr(rho), _ptr(u), 1 if dtype == torch.float32 else 0),
               "lbm_moments")
         return rho, u
+
+    # -- geometry -------------------------------------------------------------
+    def set_solid(self, solid):
+        """Solid mask [nz, ny, nx] (nonzero = solid); before initialisation."""
+        if not isinstance(solid, torch.Tensor):
+            solid = torch.from_numpy(np.ascontiguousarray(np.asarray(solid), dtype=np.uint8))
+        m = solid.to(device=self.device, dtype=torch.uint8).reshape(self.shape).contiguous()
+        self._keep = (m,)
+        check(lib().lbm_set_solid(self._h, _ptr(m)), "lbm_set_solid")
+
+    def wall_force(self):
+        """Momentum-exchange force on the walls during the last propagation."""
+        F = (ctypes.c_double * 3)()
+        check(lib().lbm_wall_force(self._h, F), "lbm_wall_force")
+        return [F[0], F[1], F[2]]
 
     # -- discrete adjoint ----------------------------------------------------
     @property

@@ -15,9 +15,9 @@ import math
 
 import numpy as np
 
-D2Q9, D3Q19 = 0, 1
+D2Q9, D3Q19, D3Q27 = 0, 1, 2
 PERIODIC, SOLID_ENDS, WALLS_OUTSIDE = 0, 1, 2
-Q_OF = {D2Q9: 9, D3Q19: 19}
+Q_OF = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 
 
 def _grid(n):
@@ -138,3 +138,13 @@ def random_fourier_field(n=128, modes=8, kmax=4, amplitude=0.02, seed=11, dims=3
             u[d] += amplitude * a[d] * c
     rho = np.ones((nzs, n, n))
     return rho, u
+
+
+def sphere_mask(dims, center, radius):
+    """Solid nodes of a sphere: |x - center| <= radius (node coordinates).
+    The paper's validation obstacle is r = 8 at (64, 64, 64) in a
+    512 x 128 x 128 box (Sec. 5)."""
+    nx, ny, nz = dims
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r2 = (x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2
+    return (r2 <= radius * radius).astype(np.uint8)

@@ -31,8 +31,10 @@ def inputs(lattice, dims, kind="tg", seed=2, noise_amp=1e-6, bc=(0, 0, 0), U0=0.
     return rho, u, noise
 
 
-def run_oracle(lattice, dims, tau, force, bc, rho, u, noise, steps):
+def run_oracle(lattice, dims, tau, force, bc, rho, u, noise, steps, solid=None):
     s = oracle.Sim(lattice, *dims, tau=tau, force=force, bc=bc)
+    if solid is not None:
+        s.set_solid(solid)
     s.init_equilibrium(rho, u, noise)
     s.step(steps)
     f = s.get_populations()
@@ -43,8 +45,10 @@ def run_oracle(lattice, dims, tau, force, bc, rho, u, noise, steps):
 
 
 def run_gpu(lattice, dims, tau, force, bc, rho, u, noise, steps, storage="f64", aa=False,
-            reduce=True):
+            reduce=True, solid=None):
     sim = lbm.LBM(lattice, *dims, tau, force=force, bc=bc, storage=storage, aa=aa)
+    if solid is not None:
+        sim.set_solid(solid)
     sim.init_equilibrium(rho, u, noise)
     sim.step(steps)
     f = sim.get_populations().cpu().numpy()
@@ -64,7 +68,7 @@ def window_indices(center, half, n, periodic):
 
 
 def sampled_window_check(f_gpu_dev, u_gpu_dev, lattice, dims, tau, force, bc, rho, u, noise,
-                         steps, centers):
+                         steps, centers, solid=None):
     """Compares GPU outputs after ``steps`` steps at sample nodes with an oracle
     run on the dependency window of each node (half-width = steps on periodic
     axes, the full extent on wall axes).  Returns the worst errors of f and u
@@ -85,9 +89,11 @@ def sampled_window_check(f_gpu_dev, u_gpu_dev, lattice, dims, tau, force, bc, rh
         n_w = noise[(slice(None),) + sub] if noise is not None else None
         wdims = (len(ix), len(iy), len(iz))
         wbc = tuple(W.PERIODIC if (b == W.PERIODIC) else b for b in bc)
+        s_w = None if solid is None else np.ascontiguousarray(solid[sub])
         f_or, _, u_or, _ = run_oracle(lattice, wdims, tau, force, wbc, np.ascontiguousarray(r_w),
                                       np.ascontiguousarray(u_w),
-                                      None if n_w is None else np.ascontiguousarray(n_w), steps)
+                                      None if n_w is None else np.ascontiguousarray(n_w), steps,
+                                      solid=s_w)
         f_ref = f_or[:, oz, oy, ox]
         u_ref = u_or[:, oz, oy, ox]
         f_got = f_gpu_dev[:, cz, cy, cx].cpu().numpy()

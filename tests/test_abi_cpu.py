@@ -32,7 +32,8 @@ def test_header_functions_are_exported():
 
 def test_header_enums_match_binding():
     text = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    for name, val in [("LBM_D2Q9", lbm.D2Q9), ("LBM_D3Q19", lbm.D3Q19), ("LBM_F64", lbm.F64),
+    for name, val in [("LBM_D2Q9", lbm.D2Q9), ("LBM_D3Q19", lbm.D3Q19), ("LBM_D3Q27", lbm.D3Q27),
+                      ("LBM_F64", lbm.F64),
                       ("LBM_F32", lbm.F32), ("LBM_F16_DEV", lbm.F16_DEV),
                       ("LBM_BF16_DEV", lbm.BF16_DEV), ("LBM_PERIODIC", lbm.PERIODIC),
                       ("LBM_SOLID_ENDS", lbm.SOLID_ENDS), ("LBM_WALLS_OUTSIDE", lbm.WALLS_OUTSIDE),
@@ -72,7 +73,7 @@ def test_create_rejects_bad_arguments(kw):
 
 def test_create_accepts_and_sizes():
     L = lbm.lib()
-    for lattice, nz, Q in ((lbm.D2Q9, 1, 9), (lbm.D3Q19, 5, 19)):
+    for lattice, nz, Q in ((lbm.D2Q9, 1, 9), (lbm.D3Q19, 5, 19), (lbm.D3Q27, 3, 27)):
         for storage, size in ((lbm.F64, 8), (lbm.F32, 4), (lbm.F16_DEV, 2), (lbm.BF16_DEV, 2)):
             st, h = _create(lattice=lattice, nx=7, ny=6, nz=nz, storage=storage)
             assert st == lbm.OK
@@ -105,6 +106,9 @@ def test_calls_before_bind_fail_without_device_work():
     assert L.lbm_set_populations(h, None) == lbm.ENOTBOUND
     assert L.lbm_init_equilibrium(h, None, None, None) == lbm.ENOTBOUND
     assert L.lbm_forward_record(h, 4, 2, None) == lbm.ENOTBOUND
+    assert L.lbm_set_solid(h, None) == lbm.ENOTBOUND
+    F = (ctypes.c_double * 3)()
+    assert L.lbm_wall_force(h, F) == lbm.ENOTBOUND
     assert L.lbm_adjoint(h, 4, 2, None, None, None, None, None, None, None) == lbm.ENOTBOUND
     assert b"lbm_bind" in L.lbm_last_error()
     assert L.lbm_step(None, 1) == lbm.EINVAL

@@ -121,19 +121,24 @@ def test_mask_equals_axis_walls_bitwise_and_force_balance(walls):
 @pytest.mark.parametrize("lattice", [W.D3Q19, W.D3Q27])
 def test_sphere_drag_balances_body_force(lattice):
     """Sphere in a periodic box driven by g_x: at steady state the drag on
-    the sphere (the only wall) equals V_fluid g to 1e-8.  The mean flow
-    relaxes with a time constant of ~1400 steps here (5.6e-7 short of the
-    balance after 20000 steps), so the run is 60000 steps."""
+    the sphere (the only wall), averaged over two consecutive propagations,
+    equals V_fluid g to 1e-8.  The force per propagation carries a
+    persistent period-2 oscillation (+-5.6e-7 relative here, with constant
+    total momentum; the CPU oracle shows the same), so one step alone is not
+    the balance."""
     dims, g, tau = (24, 20, 20), 1e-6, 0.9
     solid = W.sphere_mask(dims, (12, 10, 10), 4.0)
     sim = lbm.LBM(lattice, *dims, tau, force=(g, 0, 0))
     sim.set_solid(solid)
     nx, ny, nz = dims
     sim.init_equilibrium(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
-    sim.step(60000)
-    F = np.asarray(sim.wall_force())
+    sim.step(20000)
+    F1 = np.asarray(sim.wall_force())
+    sim.step(1)
+    F2 = np.asarray(sim.wall_force())
+    F = 0.5 * (F1 + F2)
     V = nx * ny * nz - int(solid.sum())
-    print(f"Q{lattice} sphere: F/(V g) = {F / (V * g)}")
+    print(f"Q{lattice} sphere: F/(V g) = {F / (V * g)}, oscillation {(F1[0] - F2[0]) / (2 * V * g):.2e}")
     assert abs(F[0] / (V * g) - 1) < 1e-8
     assert np.abs(F[1:]).max() < 1e-8 * V * g
 

@@ -600,7 +600,9 @@ def test_wall_force_balances_body_force_in_a_channel(lattice, walls):
 @pytest.mark.parametrize("lattice", [oracle.D3Q19, oracle.D3Q27])
 def test_wall_force_on_an_obstacle_balances_body_force(lattice):
     """A block obstacle in a periodic box driven by a body force: at steady
-    state the drag on the obstacle equals V_fluid * g (the only walls)."""
+    state the drag on the obstacle, averaged over two consecutive
+    propagations (the per-step force can carry a persistent period-2
+    oscillation around obstacles), equals V_fluid * g."""
     dims = (8, 7, 6)
     g, tau = 1e-6, 0.9
     s = oracle.Sim(lattice, *dims, tau=tau, force=(g, 0, 0))
@@ -608,7 +610,9 @@ def test_wall_force_on_an_obstacle_balances_body_force(lattice):
     fluid = s.geometry()
     s.init_equilibrium(np.ones(fluid.shape), np.zeros((3,) + fluid.shape))
     s.step(6000)
-    F = s.wall_force()
+    F1 = s.wall_force()
+    s.step(1)
+    F = 0.5 * (F1 + s.wall_force())
     V = fluid.sum()
     assert abs(F[0] / (V * g) - 1) < 1e-8
     assert np.abs(F[1:]).max() < 1e-8 * V * g

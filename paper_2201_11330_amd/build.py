@@ -6,14 +6,15 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = [os.path.join(PKG, "csrc", "lbm.hip")]
+SOURCES = [os.path.join(PKG, "csrc", name) for name in
+           ("lbm.hip", "lattice_d2q9.hip", "lattice_d3q19.hip", "lattice_d3q27.hip")]
+BUILD_DIR = os.path.join(PKG, "_build")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # Contract a*b+c into FMA only within one expression (C semantics), so the
     # same source expression rounds the same way in every kernel.
     "-ffp-contract=on",
@@ -23,19 +24,40 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp", *SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, cwd=PKG, capture_output=True, text=True)
+def _filtered(text):
     # hipcc's host pass warns that it does not know the packed-fp32 feature.
-    noise = "packed-fp32-ops"
-    msg = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if noise not in l)
+    return "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles each translation unit to an object in parallel, then links."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    jobs, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+        cmd = [hipcc, *HIPCC_FLAGS, "-c", "-I", os.path.join(ROOT, "include"), "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        jobs.append((cmd, subprocess.Popen(cmd, cwd=PKG, stdout=subprocess.PIPE,
+                                           stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    failed = []
+    for cmd, proc in jobs:
+        out, _ = proc.communicate()
+        msg = _filtered(out or "")
+        if proc.returncode != 0:
+            failed.append(f"{' '.join(cmd)}\n{msg}")
+        elif verbose and msg.strip():
+            print(msg)
+    if failed:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(failed))
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
+    if verbose:
+        print(" ".join(link), flush=True)
+    res = subprocess.run(link, cwd=PKG, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{msg}")
-    if verbose and msg.strip():
-        print(msg)
+        raise RuntimeError(f"link failed ({res.returncode}):\n{_filtered(res.stdout + res.stderr)}")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -1,0 +1,305 @@
+// Kernel launches of one lattice kind and storage type, instantiated once per
+// lattice kind in its own translation unit (lattice_*.hip).
+#pragma once
+
+#include "context.hpp"
+
+namespace imexlbm {
+
+// Kernel instantiations of one lattice and storage.
+template <int L, class S>
+struct Impl {
+    template <bool W, bool F>
+    static void step_ab(lbm_ctx* c, const S* src, S* dst)
+    {
+        hipLaunchKernelGGL((k_step_ab<L, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, src, dst,
+                           step_args<typename Store<S>::C>(c));
+    }
+    template <bool W, bool F>
+    static void step_aa(lbm_ctx* c, S* A, bool odd)
+    {
+        if (odd)
+            hipLaunchKernelGGL((k_step_aa_odd<L, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, A,
+                               step_args<typename Store<S>::C>(c));
+        else
+            hipLaunchKernelGGL((k_step_aa_even<L, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, A,
+                               step_args<typename Store<S>::C>(c));
+    }
+
+    // Captures kGraphSteps steps starting from an even step count (buffer 0
+    // current, AA even parity) on a private stream; the context's launch
+    // stream and counters are restored afterwards.
+    static lbm_status capture(lbm_ctx* c)
+    {
+        if (!c->capture_stream) LBM_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipStream_t saved_stream = c->stream;
+        const int saved_cur = c->cur;
+        const long long saved_steps = c->steps;
+        c->stream = c->capture_stream;
+        c->cur = 0;
+        c->steps = 0;
+        const lbm_status st = eager(c, kGraphSteps);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->capture_stream, &g);
+        c->stream = saved_stream;
+        c->cur = saved_cur;
+        c->steps = saved_steps;
+        if (st != LBM_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != LBM_OK ? st : hip_fail(e, "hipStreamEndCapture");
+        }
+        c->graph = g;
+        e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(c->graph);
+            c->graph = nullptr;
+            c->graph_exec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        return LBM_OK;
+    }
+
+    static lbm_status step(lbm_ctx* c, int n)
+    {
+        if (!c->use_graph || n < kGraphSteps) return eager(c, n);
+        if (c->steps & 1) {  // align to the captured parity
+            lbm_status st = eager(c, 1);
+            if (st) return st;
+            --n;
+        }
+        if (!c->graph_exec) {
+            lbm_status st = capture(c);
+            if (st) return st;
+        }
+        for (; n >= kGraphSteps; n -= kGraphSteps) {
+            LBM_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+            c->steps += kGraphSteps;
+        }
+        return eager(c, n);
+    }
+
+    static lbm_status eager(lbm_ctx* c, int n)
+    {
+        for (int i = 0; i < n; ++i) {
+            if (c->aa) {
+                S* A = static_cast<S*>(c->buf[0]);
+                const bool odd = c->steps & 1;
+                if (c->walls)
+                    c->force ? step_aa<true, true>(c, A, odd) : step_aa<true, false>(c, A, odd);
+                else
+                    c->force ? step_aa<false, true>(c, A, odd) : step_aa<false, false>(c, A, odd);
+            } else {
+                const S* src = static_cast<const S*>(c->buf[c->cur]);
+                S* dst = static_cast<S*>(c->buf[1 - c->cur]);
+                if (c->walls)
+                    c->force ? step_ab<true, true>(c, src, dst) : step_ab<true, false>(c, src, dst);
+                else
+                    c->force ? step_ab<false, true>(c, src, dst) : step_ab<false, false>(c, src, dst);
+                c->cur = 1 - c->cur;
+            }
+            ++c->steps;
+        }
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    // One two-lattice step between explicit buffers.
+    static void step_between_t(lbm_ctx* c, const S* src, S* dst)
+    {
+        if (c->walls)
+            c->force ? step_ab<true, true>(c, src, dst) : step_ab<true, false>(c, src, dst);
+        else
+            c->force ? step_ab<false, true>(c, src, dst) : step_ab<false, false>(c, src, dst);
+    }
+
+    using C = typename Store<S>::C;
+
+    static AdjArgs<C> adj_args(const lbm_ctx* c)
+    {
+        AdjArgs<C> p;
+        p.g = dims_of(c);
+        p.bx_shift = c->bx_shift;
+        p.omega = C(c->omega);
+        for (int d = 0; d < 3; ++d) p.F[d] = C(c->F[d]);
+        p.half = C(1.0 - 0.5 * c->omega);
+        return p;
+    }
+
+    template <bool W, bool F>
+    static void adj_step(lbm_ctx* c, const S* g, const C* lin, C* lout, double* acc)
+    {
+        hipLaunchKernelGGL((k_adjoint_step<L, S, W, F>), c->grid, c->block, 0, c->stream, g, lin, lout,
+                           acc, adj_args(c));
+    }
+
+    // Backward sweep over n steps with checkpoints every k steps; see
+    // lbm_adjoint.  ws holds (k-1) state buffers, two lambda fields and the
+    // per-workgroup accumulators.
+    static lbm_status adjoint(lbm_ctx* c, int n, int k, const void* ckpt, void* ws,
+                              const double* u0, const double* ubar, double* u0bar, double* out4)
+    {
+        const WorkspaceLayout W = workspace_layout(c, k);
+        char* w = static_cast<char*>(ws);
+        C* lam[2] = {reinterpret_cast<C*>(w + W.lam0), reinterpret_cast<C*>(w + W.lam1)};
+        double* acc = reinterpret_cast<double*>(w + W.acc);
+        double* result = reinterpret_cast<double*>(w + W.result);
+        const Dims g = dims_of(c);
+        hipLaunchKernelGGL(k_fill_zero, dim3((W.acc_doubles + 255) / 256), dim3(256), 0, c->stream, acc,
+                           W.acc_doubles);
+        if (c->walls)
+            hipLaunchKernelGGL((k_adjoint_seed<L, S, true>), c->grid, c->block, 0, c->stream, ubar, lam[0],
+                               acc, g, c->bx_shift);
+        else
+            hipLaunchKernelGGL((k_adjoint_seed<L, S, false>), c->grid, c->block, 0, c->stream, ubar, lam[0],
+                               acc, g, c->bx_shift);
+        int cur = 0;
+        const char* ck = static_cast<const char*>(ckpt);
+        for (int s = n / k - 1; s >= 0; --s) {
+            const S* state0 = reinterpret_cast<const S*>(ck + size_t(s) * W.state_bytes);
+            auto state = [&](int j) -> const S* {
+                return j == 0 ? state0 : reinterpret_cast<const S*>(w + W.seg + size_t(j - 1) * W.state_bytes);
+            };
+            for (int j = 1; j < k; ++j)
+                step_between_t(c, state(j - 1), const_cast<S*>(state(j)));
+            for (int j = k - 1; j >= 0; --j) {
+                if (c->walls)
+                    c->force ? adj_step<true, true>(c, state(j), lam[cur], lam[1 - cur], acc)
+                             : adj_step<true, false>(c, state(j), lam[cur], lam[1 - cur], acc);
+                else
+                    c->force ? adj_step<false, true>(c, state(j), lam[cur], lam[1 - cur], acc)
+                             : adj_step<false, false>(c, state(j), lam[cur], lam[1 - cur], acc);
+                cur = 1 - cur;
+            }
+        }
+        if (c->walls)
+            hipLaunchKernelGGL((k_adjoint_init_map<L, S, true>), c->grid, c->block, 0, c->stream, lam[cur], u0,
+                               u0bar, g, c->bx_shift);
+        else
+            hipLaunchKernelGGL((k_adjoint_init_map<L, S, false>), c->grid, c->block, 0, c->stream, lam[cur], u0,
+                               u0bar, g, c->bx_shift);
+        hipLaunchKernelGGL(k_adjoint_sum, dim3(1), dim3(256), 0, c->stream, acc, W.nblocks, result);
+        LBM_HIP(hipGetLastError());
+        LBM_HIP(hipMemcpyAsync(out4, result, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        LBM_HIP(hipStreamSynchronize(c->stream));
+        return LBM_OK;
+    }
+
+    static lbm_status build_links(lbm_ctx* c, const unsigned char* mask)
+    {
+        Dims g = dims_of(c);
+        g.links = nullptr;
+        hipLaunchKernelGGL((k_build_links<L>), c->grid, c->block, 0, c->stream, mask, c->links, g,
+                           c->bx_shift);
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    static lbm_status wall_force(lbm_ctx* c)
+    {
+        IoArgs p = io_args(c);
+        const S* A = static_cast<const S*>(c->buf[c->cur]);
+        hipLaunchKernelGGL((k_wall_force<L, S>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, c->stream,
+                           A, c->d_partials, p);
+        hipLaunchKernelGGL(k_sum3, dim3(1), dim3(kReduceThreads), 0, c->stream, c->d_partials,
+                           kReduceBlocks, c->d_partials + 5 * size_t(kReduceBlocks));
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    static lbm_status import(lbm_ctx* c, const double* f, const double* rho, const double* u,
+                             const double* noise)
+    {
+        IoArgs p = io_args(c);
+        S* A = static_cast<S*>(c->buf[c->cur]);
+        if (c->walls)
+            hipLaunchKernelGGL((k_import<L, S, true>), c->grid, c->block, 0, c->stream, A, f, rho, u,
+                               noise, p);
+        else
+            hipLaunchKernelGGL((k_import<L, S, false>), c->grid, c->block, 0, c->stream, A, f, rho, u,
+                               noise, p);
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    static lbm_status export_f(lbm_ctx* c, double* f)
+    {
+        IoArgs p = io_args(c);
+        const S* A = static_cast<const S*>(c->buf[c->cur]);
+        if (c->walls)
+            hipLaunchKernelGGL((k_export<L, S, true>), c->grid, c->block, 0, c->stream, A, f, p);
+        else
+            hipLaunchKernelGGL((k_export<L, S, false>), c->grid, c->block, 0, c->stream, A, f, p);
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    template <class O>
+    static void moments_t(lbm_ctx* c, O* rho, O* u)
+    {
+        IoArgs p = io_args(c);
+        const S* A = static_cast<const S*>(c->buf[c->cur]);
+        if (c->walls)
+            hipLaunchKernelGGL((k_moments<L, S, true, O>), c->grid, c->block, 0, c->stream, A, rho, u,
+                               p);
+        else
+            hipLaunchKernelGGL((k_moments<L, S, false, O>), c->grid, c->block, 0, c->stream, A, rho,
+                               u, p);
+    }
+
+    static lbm_status moments(lbm_ctx* c, void* rho, void* u, int f32)
+    {
+        if (f32)
+            moments_t<float>(c, static_cast<float*>(rho), static_cast<float*>(u));
+        else
+            moments_t<double>(c, static_cast<double*>(rho), static_cast<double*>(u));
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    static lbm_status reduce(lbm_ctx* c)
+    {
+        IoArgs p = io_args(c);
+        const S* A = static_cast<const S*>(c->buf[c->cur]);
+        if (c->walls)
+            hipLaunchKernelGGL((k_reduce_partials<L, S, true>), dim3(kReduceBlocks),
+                               dim3(kReduceThreads), 0, c->stream, A, c->d_partials, p);
+        else
+            hipLaunchKernelGGL((k_reduce_partials<L, S, false>), dim3(kReduceBlocks),
+                               dim3(kReduceThreads), 0, c->stream, A, c->d_partials, p);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, c->stream, c->d_partials,
+                           kReduceBlocks, int(Store<S>::kDeviation),
+                           c->d_partials + 5 * size_t(kReduceBlocks));
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    static lbm_status step_between(lbm_ctx* c, const void* src, void* dst)
+    {
+        step_between_t(c, static_cast<const S*>(src), static_cast<S*>(dst));
+        LBM_HIP(hipGetLastError());
+        return LBM_OK;
+    }
+
+    static const Ops* ops()
+    {
+        static const Ops table = {&step, &import, &export_f, &moments, &reduce, &adjoint,
+                                  &build_links, &wall_force, &step_between};
+        return &table;
+    }
+};
+
+template <int L>
+const Ops* make_ops(lbm_storage s)
+{
+    switch (s) {
+    case LBM_F64: return Impl<L, double>::ops();
+    case LBM_F32: return Impl<L, float>::ops();
+    case LBM_F16_DEV: return Impl<L, __half>::ops();
+    case LBM_BF16_DEV: return Impl<L, __hip_bfloat16>::ops();
+    }
+    return nullptr;
+}
+
+}  // namespace imexlbm

@@ -631,7 +631,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const S* __r
 // Sums the block partials in block order with one block; out[0..3] = mass
 // (plus the fluid-node count for deviation storage), kinetic energy
 // (rho0/2) sum |u|^2, max |u|, non-finite count.
-__global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partials,
+static __global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partials,
                                                                  int nblocks, int deviation,
                                                                  double* __restrict__ out)
 {
@@ -667,7 +667,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* _
 }
 
 // Sums slots 0..2 of the block partials in block order (one workgroup).
-__global__ __launch_bounds__(kReduceThreads) void k_sum3(const double* __restrict__ partials,
+static __global__ __launch_bounds__(kReduceThreads) void k_sum3(const double* __restrict__ partials,
                                                          int nblocks, double* __restrict__ out)
 {
     __shared__ double s[3][kReduceThreads];

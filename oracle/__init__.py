@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
-PERIODIC, SOLID_ENDS, WALLS_OUTSIDE = 0, 1, 2
+PERIODIC, SOLID_ENDS, WALLS_OUTSIDE, WALLS_NODAL = 0, 1, 2, 3
 _QOF = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -44,15 +44,17 @@ def _load():
     lib.orc_geometry.argtypes = [vp, ctypes.POINTER(ctypes.c_ubyte)]
     lib.orc_reduce.argtypes = [vp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_long)]
     lib.orc_lattice_tables.argtypes = [ctypes.c_int, _ip, _ip, _ip, _dp]
-    lib.orc_equilibrium_node.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
-    lib.orc_collide_node.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+    lib.orc_equilibrium_node.argtypes = [ctypes.c_int, ctypes.c_double, _dp, ctypes.c_int, _dp]
+    lib.orc_collide_node.argtypes = [ctypes.c_int, ctypes.c_double, _dp, ctypes.c_int, _dp, _dp]
+    lib.orc_set_compressible.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.orc_collide_node_cs.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+    _up = ctypes.POINTER(ctypes.c_ubyte)
     lib.orc_cs_objective.argtypes = (
-        [ctypes.c_int] * 4 + [ctypes.c_double, ctypes.c_double, _dp, _dp, _ip, _dp, _dp, _dp, _dp,
-                              ctypes.c_int, ctypes.c_double, _dp, _dp, _dp])
+        [ctypes.c_int] * 4 + [ctypes.c_double, ctypes.c_double, _dp, _dp, _ip, _up, ctypes.c_int,
+                              _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp])
     lib.orc_adjoint.argtypes = (
-        [ctypes.c_int] * 4 + [ctypes.c_double, _dp, _ip, _dp, _dp, _dp, ctypes.c_int, _dp, _dp,
-                              _dp, _dp])
+        [ctypes.c_int] * 4 + [ctypes.c_double, _dp, _ip, _up, ctypes.c_int, _dp, _dp, _dp,
+                              ctypes.c_int, _dp, _dp, _dp, _dp])
     lib.orc_set_solid.argtypes = [vp, ctypes.POINTER(ctypes.c_ubyte)]
     lib.orc_wall_force.argtypes = [vp, _dp]
     lib.orc_num_threads.argtypes = []
@@ -106,19 +108,21 @@ def lattice_tables(lattice):
     return e[: Q.value].astype(np.int64), t[: Q.value].copy()
 
 
-def equilibrium_node(lattice, rho, u):
+def equilibrium_node(lattice, rho, u, compressible=False):
     lib = _load()
     Q = _QOF[lattice]
     out = np.zeros(Q)
-    _check(lib.orc_equilibrium_node(lattice, float(rho), _d(_vec3(u)), _d(out)), "equilibrium")
+    _check(lib.orc_equilibrium_node(lattice, float(rho), _d(_vec3(u)), int(compressible), _d(out)),
+           "equilibrium")
     return out
 
 
-def collide_node(lattice, tau, F, f):
+def collide_node(lattice, tau, F, f, compressible=False):
     lib = _load()
     f = _f64(f)
     out = np.zeros_like(f)
-    _check(lib.orc_collide_node(lattice, float(tau), _d(_vec3(F)), _d(f), _d(out)), "collide")
+    _check(lib.orc_collide_node(lattice, float(tau), _d(_vec3(F)), int(compressible), _d(f),
+                                _d(out)), "collide")
     return out
 
 
@@ -138,7 +142,8 @@ def collide_node_complex(lattice, tau, F, f):
 class Sim:
     """The oracle's simulation state: paper-order FP64 time stepping."""
 
-    def __init__(self, lattice, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), bc=(0, 0, 0)):
+    def __init__(self, lattice, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), bc=(0, 0, 0),
+                 compressible=False):
         self._lib = _load()
         self.lattice = lattice
         self.Q = _QOF[lattice]
@@ -151,6 +156,8 @@ class Sim:
         _check(self._lib.orc_create(lattice, nx, ny, nz, float(tau), _d(self.force),
                                     _bc3(self.bc), ctypes.byref(h)), "create")
         self._h = h
+        if compressible:
+            _check(self._lib.orc_set_compressible(self._h, 1), "set_compressible")
 
     def close(self):
         if self._h:
@@ -213,8 +220,16 @@ class Sim:
         return {"mass": m.value, "ke": k.value, "umax": um.value, "nonfinite": bad.value}
 
 
+def _mask(solid, shape):
+    if solid is None:
+        return None, None
+    m = np.ascontiguousarray(np.asarray(solid).reshape(shape), dtype=np.uint8)
+    return m, m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
+
+
 def cs_objective(lattice, dims, tau, force, bc, rho0, u0, u_tgt, nsteps, *, dtau=0.0,
-                 dforce=(0.0, 0.0, 0.0), du0=None, noise=None, h=1e-30):
+                 dforce=(0.0, 0.0, 0.0), du0=None, noise=None, h=1e-30, solid=None,
+                 compressible=False):
     """(J, dJ) with J = 1/2 sum |u^N - u_tgt|^2 and dJ its complex-step
     derivative along (du0, dtau, dforce)."""
     lib = _load()
@@ -227,14 +242,17 @@ def cs_objective(lattice, dims, tau, force, bc, rho0, u0, u_tgt, nsteps, *, dtau
     du0 = np.zeros_like(u0) if du0 is None else _f64(du0, (3,) + shape)
     noise = _f64(noise, (Q,) + shape)
     J, dJ = ctypes.c_double(), ctypes.c_double()
+    keep, mp = _mask(solid, shape)
     _check(lib.orc_cs_objective(lattice, nx, ny, nz, float(tau), float(dtau), _d(_vec3(force)),
-                                _d(_vec3(dforce)), _bc3(bc), _d(rho0), _d(u0), _d(du0), _d(noise),
+                                _d(_vec3(dforce)), _bc3(bc), mp, int(compressible), _d(rho0),
+                                _d(u0), _d(du0), _d(noise),
                                 int(nsteps), float(h), _d(u_tgt), ctypes.byref(J),
                                 ctypes.byref(dJ)), "cs_objective")
     return J.value, dJ.value
 
 
-def adjoint(lattice, dims, tau, force, bc, rho0, u0, ubar, nsteps, noise=None):
+def adjoint(lattice, dims, tau, force, bc, rho0, u0, ubar, nsteps, noise=None, *, solid=None,
+            compressible=False):
     """Gradients (u0bar [3,nz,ny,nx], taubar, Fbar [3]) of a functional whose
     derivative with respect to the final velocity u^N is ``ubar``."""
     lib = _load()
@@ -248,7 +266,9 @@ def adjoint(lattice, dims, tau, force, bc, rho0, u0, ubar, nsteps, noise=None):
     u0bar = np.zeros((3,) + shape)
     taubar = ctypes.c_double()
     Fbar = np.zeros(3)
-    _check(lib.orc_adjoint(lattice, nx, ny, nz, float(tau), _d(_vec3(force)), _bc3(bc), _d(rho0),
-                           _d(u0), _d(noise), int(nsteps), _d(ubar), _d(u0bar),
+    keep, mp = _mask(solid, shape)
+    _check(lib.orc_adjoint(lattice, nx, ny, nz, float(tau), _d(_vec3(force)), _bc3(bc), mp,
+                           int(compressible), _d(rho0), _d(u0), _d(noise), int(nsteps), _d(ubar),
+                           _d(u0bar),
                            ctypes.byref(taubar), _d(Fbar)), "adjoint")
     return u0bar, taubar.value, Fbar

@@ -147,6 +147,7 @@ struct orc_sim {
     int bc[3];
     double tau, omega;
     double F[3];
+    int comp;           /* 1: weakly compressible equilibrium of Eq. (feq) */
     unsigned char* geo; /* SetGeometry: 1 = fluid, 0 = solid */
     double* f;          /* post-propagation populations, AoS */
     double* fb;         /* post-collision populations, AoS */
@@ -159,23 +160,89 @@ static long node_id(const orc_sim* s, int x, int y, int z)
     return (long)x + (long)s->nx * ((long)y + (long)s->ny * (long)z);
 }
 
+#define ORC_WALL (-1)   /* x + sgn e_a is solid, or outside on a halfway-wall axis */
+#define ORC_BEYOND (-2) /* x + sgn e_a lies beyond a wall of the modified nodal scheme */
+
 /*
- * The node x + sgn*e_a seen from (x, y, z): wrapped on periodic axes, and -1
- * if it lies outside the box or is solid (the bounce-back case).
+ * The node x + sgn*e_a seen from (x, y, z): wrapped on periodic axes,
+ * ORC_BEYOND if it lies outside the box along the axis with nodal walls,
+ * ORC_WALL if it lies outside along another wall axis or is solid.
  */
 static long neighbour(const orc_sim* s, int x, int y, int z, int a, int sgn)
 {
     int c[3] = {x + sgn * s->L.e[a][0], y + sgn * s->L.e[a][1], z + sgn * s->L.e[a][2]};
     int n[3] = {s->nx, s->ny, s->nz};
+    for (int d = 0; d < 3; ++d)
+        if (s->bc[d] == ORC_WALLS_NODAL && (c[d] < 0 || c[d] >= n[d])) return ORC_BEYOND;
     for (int d = 0; d < 3; ++d) {
         if (c[d] >= 0 && c[d] < n[d]) continue;
         if (s->bc[d] == ORC_PERIODIC)
             c[d] = (c[d] % n[d] + n[d]) % n[d];
         else
-            return -1;
+            return ORC_WALL;
     }
     long id = node_id(s, c[0], c[1], c[2]);
-    return s->geo[id] ? id : -1;
+    return s->geo[id] ? id : ORC_WALL;
+}
+
+/*
+ * Where the propagation takes f_a(x) from: the slot (node, dir) of the
+ * post-collision array.
+ *  - Eq. (propagation): fb_a(x - e_a) when x - e_a is a fluid node.
+ *  - Eq. (bb), halfway (link-wise) reading: fb_abar(x) when x - e_a is solid
+ *    or outside on a halfway-wall axis.
+ *  - Eq. (bb), modified nodal reading (Sec. 2.2): on a wall node of the
+ *    nodal scheme the population whose source lies beyond the wall is
+ *    unknown after the propagation and is replaced by the one that arrived
+ *    in the opposite direction, f_a(x) = f_abar(x), i.e. the source of abar.
+ *    abar itself points beyond the wall, so its source is inside the box
+ *    along that axis and the rule does not recurse further.
+ */
+static void pull_source(const orc_sim* s, int x, int y, int z, int a, long* node, int* dir)
+{
+    long id = node_id(s, x, y, z);
+    long src = neighbour(s, x, y, z, a, -1);
+    if (src == ORC_BEYOND) {
+        a = opposite(&s->L, a);
+        src = neighbour(s, x, y, z, a, -1);
+    }
+    if (src >= 0) {
+        *node = src;
+        *dir = a;
+    } else {
+        *node = id;
+        *dir = opposite(&s->L, a);
+    }
+}
+
+/* Eq. (bb) on the wall nodes of the nodal scheme: the unknown populations of
+ * a post-propagation state are copies of the opposite ones. */
+static void nodal_fill_r(const orc_sim* s, double* f)
+{
+    const int Q = s->L.Q;
+    for (int z = 0; z < s->nz; ++z)
+        for (int y = 0; y < s->ny; ++y)
+            for (int x = 0; x < s->nx; ++x) {
+                long id = node_id(s, x, y, z);
+                if (!s->geo[id]) continue;
+                for (int a = 0; a < Q; ++a)
+                    if (neighbour(s, x, y, z, a, -1) == ORC_BEYOND)
+                        f[id * Q + a] = f[id * Q + opposite(&s->L, a)];
+            }
+}
+
+static void nodal_fill_c(const orc_sim* s, double complex* f)
+{
+    const int Q = s->L.Q;
+    for (int z = 0; z < s->nz; ++z)
+        for (int y = 0; y < s->ny; ++y)
+            for (int x = 0; x < s->nx; ++x) {
+                long id = node_id(s, x, y, z);
+                if (!s->geo[id]) continue;
+                for (int a = 0; a < Q; ++a)
+                    if (neighbour(s, x, y, z, a, -1) == ORC_BEYOND)
+                        f[id * Q + a] = f[id * Q + opposite(&s->L, a)];
+            }
 }
 
 static int validate(int lattice, int nx, int ny, int nz, double tau, const double F[3],
@@ -184,13 +251,19 @@ static int validate(int lattice, int nx, int ny, int nz, double tau, const doubl
     orc_lattice L;
     if (make_lattice(lattice, &L)) return ORC_EINVAL;
     int n[3] = {nx, ny, nz};
+    int nodal = 0;
     for (int d = 0; d < 3; ++d) {
         if (n[d] < 1) return ORC_EINVAL;
-        if (bc[d] != ORC_PERIODIC && bc[d] != ORC_SOLID_ENDS && bc[d] != ORC_WALLS_OUTSIDE)
+        if (bc[d] != ORC_PERIODIC && bc[d] != ORC_SOLID_ENDS && bc[d] != ORC_WALLS_OUTSIDE &&
+            bc[d] != ORC_WALLS_NODAL)
             return ORC_EINVAL;
-        if (bc[d] == ORC_SOLID_ENDS && n[d] < 3) return ORC_EINVAL;
+        if ((bc[d] == ORC_SOLID_ENDS || bc[d] == ORC_WALLS_NODAL) && n[d] < 3) return ORC_EINVAL;
+        nodal += bc[d] == ORC_WALLS_NODAL;
         if (!isfinite(F[d])) return ORC_EINVAL;
     }
+    /* One axis at most: on an edge shared by two nodal walls the unknown
+     * populations would be defined in terms of each other. */
+    if (nodal > 1) return ORC_EINVAL;
     if (lattice == ORC_D2Q9 && (nz != 1 || bc[2] != ORC_PERIODIC || F[2] != 0.0))
         return ORC_EINVAL;
     if (!(tau > 0.5)) return ORC_EINVAL; /* +inf allowed: omega = 0 */
@@ -263,7 +336,7 @@ static void post_processing(orc_sim* s)
             s->u[id * 3 + 0] = s->u[id * 3 + 1] = s->u[id * 3 + 2] = 0.0;
             continue;
         }
-        node_moments_r(&s->L, s->F, s->f + id * Q, s->rho + id, s->u + id * 3);
+        node_moments_r(&s->L, s->F, s->f + id * Q, s->comp, s->rho + id, s->u + id * 3);
     }
 }
 
@@ -275,16 +348,14 @@ static void collision(orc_sim* s)
 #pragma omp parallel for schedule(static)
     for (long id = 0; id < s->N; ++id) {
         if (!s->geo[id]) continue;
-        node_relax_r(&s->L, s->omega, s->F, s->rho[id], s->u + id * 3, s->f + id * Q,
+        node_relax_r(&s->L, s->omega, s->F, s->rho[id], s->u + id * 3, s->comp, s->f + id * Q,
                      s->fb + id * Q);
     }
 }
 
 /*
  * BoundaryCondition + Propagation (Eq. (bb), Eq. (propagation)): each fluid
- * node pulls f_a(x) = fb_a(x - e_a); when x - e_a is solid (or outside the
- * box on a wall axis) the population that left x towards it comes back
- * reversed, f_a(x) = fb_abar(x) -- the link-wise reading of Eq. (bb).
+ * node pulls f_a(x) from the slot that pull_source names.
  */
 static void propagation(orc_sim* s)
 {
@@ -296,9 +367,10 @@ static void propagation(orc_sim* s)
                 long id = node_id(s, x, y, z);
                 if (!s->geo[id]) continue;
                 for (int a = 0; a < Q; ++a) {
-                    long src = neighbour(s, x, y, z, a, -1);
-                    s->f[id * Q + a] =
-                        src >= 0 ? s->fb[src * Q + a] : s->fb[id * Q + opposite(&s->L, a)];
+                    long node;
+                    int dir;
+                    pull_source(s, x, y, z, a, &node, &dir);
+                    s->f[id * Q + a] = s->fb[node * Q + dir];
                 }
             }
 }
@@ -316,10 +388,11 @@ int orc_init_equilibrium(orc_sim* s, const double* rho, const double* u, const d
         }
         double uu[3] = {u[id], u[N + id], u[2 * N + id]};
         double feq[ORC_QMAX];
-        node_equilibrium_r(&s->L, rho[id], uu, feq);
+        node_equilibrium_r(&s->L, rho[id], uu, s->comp, feq);
         for (int a = 0; a < Q; ++a)
             s->f[id * Q + a] = noise ? feq[a] + noise[(long)a * N + id] : feq[a];
     }
+    nodal_fill_r(s, s->f);
     post_processing(s);
     return 0;
 }
@@ -330,6 +403,9 @@ int orc_set_populations(orc_sim* s, const double* f)
     for (long id = 0; id < s->N; ++id)
         for (int a = 0; a < Q; ++a)
             s->f[id * Q + a] = s->geo[id] ? f[(long)a * s->N + id] : 0.0;
+    /* f^n is a post-propagation state: on nodal wall nodes its unknown
+     * populations are the opposite ones (Eq. (bb)); given values are ignored. */
+    nodal_fill_r(s, s->f);
     post_processing(s);
     return 0;
 }
@@ -398,7 +474,8 @@ int orc_set_solid(orc_sim* s, const unsigned char* solid)
  *   F = sum_x sum_a [f*_a(x, t) + f_abar(x, t + dt)] e_a.
  * Reading: with the link-wise bounce-back the returning population is the
  * one at x after the propagation (the paper writes it at the wall-side
- * node of the nodal scheme).
+ * node of the nodal scheme).  Links that cross a wall of the nodal scheme
+ * are not part of the sum.
  */
 int orc_wall_force(const orc_sim* s, double F[3])
 {
@@ -410,7 +487,7 @@ int orc_wall_force(const orc_sim* s, double F[3])
                 long id = node_id(s, x, y, z);
                 if (!s->geo[id]) continue;
                 for (int a = 0; a < Q; ++a) {
-                    if (neighbour(s, x, y, z, a, +1) >= 0) continue;
+                    if (neighbour(s, x, y, z, a, +1) != ORC_WALL) continue;
                     double m = s->fb[id * Q + a] + s->f[id * Q + opposite(&s->L, a)];
                     for (int d = 0; d < 3; ++d) kahan_add(&acc[d], m * (double)s->L.e[a][d]);
                 }
@@ -421,7 +498,8 @@ int orc_wall_force(const orc_sim* s, double F[3])
 
 /*
  * Monitor analogue (Sec. 3.6): total mass sum rho, kinetic energy
- * (rho0/2) sum |u|^2 and max |u| over every fluid node, plus the number of
+ * sum (rho_m/2) |u|^2 (rho_m = rho0 in the incompressible model, rho in the
+ * compressible one) and max |u| over every fluid node, plus the number of
  * non-finite populations.
  */
 int orc_reduce(const orc_sim* s, double* mass, double* ke, double* umax, long* nonfinite)
@@ -437,13 +515,22 @@ int orc_reduce(const orc_sim* s, double* mass, double* ke, double* umax, long* n
         const double* u = s->u + id * 3;
         double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         kahan_add(&m, s->rho[id]);
-        kahan_add(&k, 0.5 * ORC_RHO0 * uu);
+        kahan_add(&k, 0.5 * (s->comp ? s->rho[id] : ORC_RHO0) * uu);
         if (sqrt(uu) > um) um = sqrt(uu);
     }
     if (mass) *mass = m.sum + m.comp;
     if (ke) *ke = k.sum + k.comp;
     if (umax) *umax = um;
     if (nonfinite) *nonfinite = bad;
+    return 0;
+}
+
+/* Selects the weakly compressible equilibrium of Eq. (feq) (comp != 0) or
+ * the incompressible one of Eq. (incompressible_feq) (comp == 0, the
+ * default); call before initialising the populations. */
+int orc_set_compressible(orc_sim* s, int comp)
+{
+    s->comp = comp ? 1 : 0;
     return 0;
 }
 
@@ -467,19 +554,20 @@ int orc_lattice_tables(int lattice, int* Q, int* D, int* e, double* t)
     return 0;
 }
 
-int orc_equilibrium_node(int lattice, double rho, const double u[3], double* feq)
+int orc_equilibrium_node(int lattice, double rho, const double u[3], int comp, double* feq)
 {
     orc_lattice L;
     if (make_lattice(lattice, &L)) return ORC_EINVAL;
-    node_equilibrium_r(&L, rho, u, feq);
+    node_equilibrium_r(&L, rho, u, comp, feq);
     return 0;
 }
 
-int orc_collide_node(int lattice, double tau, const double F[3], const double* f, double* fb)
+int orc_collide_node(int lattice, double tau, const double F[3], int comp, const double* f,
+                     double* fb)
 {
     orc_lattice L;
     if (make_lattice(lattice, &L)) return ORC_EINVAL;
-    node_collide_r(&L, 1.0 / tau, F, f, fb);
+    node_collide_r(&L, 1.0 / tau, F, comp, f, fb);
     return 0;
 }
 
@@ -491,7 +579,7 @@ int orc_collide_node_cs(int lattice, const double tau[2], const double F[6], con
     double complex Fc[3], fc[ORC_QMAX], out[ORC_QMAX];
     for (int d = 0; d < 3; ++d) Fc[d] = CMPLX(F[2 * d], F[2 * d + 1]);
     for (int a = 0; a < L.Q; ++a) fc[a] = CMPLX(f[2 * a], f[2 * a + 1]);
-    node_collide_c(&L, 1.0 / CMPLX(tau[0], tau[1]), Fc, fc, out);
+    node_collide_c(&L, 1.0 / CMPLX(tau[0], tau[1]), Fc, 0, fc, out);
     for (int a = 0; a < L.Q; ++a) {
         fb[2 * a] = creal(out[a]);
         fb[2 * a + 1] = cimag(out[a]);
@@ -503,20 +591,33 @@ int orc_collide_node_cs(int lattice, const double tau[2], const double F[6], con
 /* Derivatives: complex-step tangent of the whole run, and the discrete      */
 /* adjoint built from complex-step Jacobians of the collision.               */
 
+/* Creates the simulation the derivative entry points run on. */
+static int make_sim(int lattice, int nx, int ny, int nz, double tau, const double F[3],
+                    const int bc[3], const unsigned char* solid, int comp, orc_sim** out)
+{
+    int st = orc_create(lattice, nx, ny, nz, tau, F, bc, out);
+    if (st) return st;
+    if (solid) orc_set_solid(*out, solid);
+    orc_set_compressible(*out, comp);
+    return 0;
+}
+
 /*
- * Runs the forward model in complex arithmetic from
+ * Tangent by the complex step: runs the forward model in complex arithmetic
+ * with
  *   tau + i h dtau,  F + i h dF,  u0 + i h du0
  * and evaluates J = 1/2 sum_x sum_d (u_d^N(x) - u_tgt,d(x))^2 over the fluid
  * nodes.  Re J is the objective, Im J / h its derivative along (du0, dtau, dF)
- * to rounding (the step is polynomial in f, u0 and F and rational in tau).
+ * to rounding (the step is rational in f, u0, F and tau).
  */
 int orc_cs_objective(int lattice, int nx, int ny, int nz, double tau, double dtau,
-                     const double F[3], const double dF[3], const int bc[3], const double* rho0,
-                     const double* u0, const double* du0, const double* noise, int nsteps,
-                     double h, const double* u_tgt, double* J, double* dJ)
+                     const double F[3], const double dF[3], const int bc[3],
+                     const unsigned char* solid, int comp, const double* rho0, const double* u0,
+                     const double* du0, const double* noise, int nsteps, double h,
+                     const double* u_tgt, double* J, double* dJ)
 {
     orc_sim* s;
-    int st = orc_create(lattice, nx, ny, nz, tau, F, bc, &s);
+    int st = make_sim(lattice, nx, ny, nz, tau, F, bc, solid, comp, &s);
     if (st) return st;
     const int Q = s->L.Q;
     const long N = s->N;
@@ -539,14 +640,15 @@ int orc_cs_objective(int lattice, int nx, int ny, int nz, double tau, double dta
         }
         double complex uu[3], feq[ORC_QMAX];
         for (int d = 0; d < 3; ++d) uu[d] = CMPLX(u0[d * N + id], h * du0[d * N + id]);
-        node_equilibrium_c(&s->L, rho0[id], uu, feq);
+        node_equilibrium_c(&s->L, rho0[id], uu, s->comp, feq);
         for (int a = 0; a < Q; ++a)
             f[id * Q + a] = noise ? feq[a] + noise[(long)a * N + id] : feq[a];
     }
+    nodal_fill_c(s, f);
     for (int it = 0; it < nsteps; ++it) {
 #pragma omp parallel for schedule(static)
         for (long id = 0; id < N; ++id)
-            if (s->geo[id]) node_collide_c(&s->L, omega, Fc, f + id * Q, fb + id * Q);
+            if (s->geo[id]) node_collide_c(&s->L, omega, Fc, s->comp, f + id * Q, fb + id * Q);
 #pragma omp parallel for collapse(2) schedule(static)
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
@@ -554,8 +656,10 @@ int orc_cs_objective(int lattice, int nx, int ny, int nz, double tau, double dta
                     long id = node_id(s, x, y, z);
                     if (!s->geo[id]) continue;
                     for (int a = 0; a < Q; ++a) {
-                        long src = neighbour(s, x, y, z, a, -1);
-                        f[id * Q + a] = src >= 0 ? fb[src * Q + a] : fb[id * Q + opposite(&s->L, a)];
+                        long node;
+                        int dir;
+                        pull_source(s, x, y, z, a, &node, &dir);
+                        f[id * Q + a] = fb[node * Q + dir];
                     }
                 }
     }
@@ -563,7 +667,7 @@ int orc_cs_objective(int lattice, int nx, int ny, int nz, double tau, double dta
     for (long id = 0; id < N; ++id) {
         if (!s->geo[id]) continue;
         double complex r, uN[3];
-        node_moments_c(&s->L, Fc, f + id * Q, &r, uN);
+        node_moments_c(&s->L, Fc, f + id * Q, s->comp, &r, uN);
         for (int d = 0; d < s->L.D; ++d) {
             double complex diff = uN[d] - u_tgt[d * N + id];
             acc = acc + 0.5 * diff * diff;
@@ -580,25 +684,28 @@ int orc_cs_objective(int lattice, int nx, int ny, int nz, double tau, double dta
 #define ORC_CS_H 1e-30
 
 /*
- * Discrete adjoint of n steps.  Forward: f^0 = feq(rho_init, u0) + noise,
- * f^{k+1} = S(C(f^k; tau, F)), u^n = (sum_a e_a f^n_a + F/2)/rho0, where C is
- * the node collision and S the propagation permutation with bounce-back.
- * Given ubar = dJ/du^n, returns dJ/du0, dJ/dtau and dJ/dF by running the
+ * Discrete adjoint of n steps.  Forward: f^0 = B(feq(rho_init, u0) + noise),
+ * f^{k+1} = P(C(f^k; tau, F)), u^n = (sum_a e_a f^n_a + F/2)/rho_m, where C
+ * is the node collision, P the propagation (a linear map that reads one
+ * post-collision slot per population, see pull_source) and B the nodal
+ * replacement of Eq. (bb) (the identity without nodal walls).  Given
+ * ubar = dJ/du^n, returns dJ/du0, dJ/dtau and dJ/dF by running the
  * transposed steps backwards:
- *   lambda^n_a = e_a . ubar / rho0,         Fbar += sum_x ubar / (2 rho0)
- *   lambda*    = S^T lambda^{k+1}           (S is a permutation, S^T = S^-1)
+ *   lambda^n   = (du^n/df^n)^T ubar,         Fbar  = (du^n/dF)^T ubar
+ *   lambda*    = P^T lambda^{k+1}            (scatter-add along the pulls)
  *   lambda^k   = (dC/df)^T lambda*,  taubar += (dC/dtau)^T lambda*,
  *                                    Fbar   += (dC/dF)^T lambda*
- *   u0bar      = (dfeq/du0)^T lambda^0
+ *   u0bar      = (dfeq/du0)^T B^T lambda^0
  * with every Jacobian column taken by a complex step of h = 1e-30.
  */
 int orc_adjoint(int lattice, int nx, int ny, int nz, double tau, const double F[3],
-                const int bc[3], const double* rho0, const double* u0, const double* noise,
-                int nsteps, const double* ubar, double* u0bar, double* taubar, double Fbar[3])
+                const int bc[3], const unsigned char* solid, int comp, const double* rho0,
+                const double* u0, const double* noise, int nsteps, const double* ubar,
+                double* u0bar, double* taubar, double Fbar[3])
 {
     if (nsteps < 0) return ORC_EINVAL;
     orc_sim* s;
-    int st = orc_create(lattice, nx, ny, nz, tau, F, bc, &s);
+    int st = make_sim(lattice, nx, ny, nz, tau, F, bc, solid, comp, &s);
     if (st) return st;
     const orc_lattice* L = &s->L;
     const int Q = L->Q;
@@ -623,35 +730,49 @@ int orc_adjoint(int lattice, int nx, int ny, int nz, double tau, const double F[
     }
 
     double tb = 0.0, Fb[3] = {0.0, 0.0, 0.0};
-    /* Output map: u^n depends on f^n through sum_a e_a f_a / rho0 and on F
-     * through F/(2 rho0). */
-    for (long id = 0; id < N; ++id)
-        for (int a = 0; a < Q; ++a) {
-            double v = 0.0;
-            if (s->geo[id])
-                for (int d = 0; d < L->D; ++d) v = v + (double)L->e[a][d] * ubar[d * N + id];
-            lam[id * Q + a] = v / ORC_RHO0;
+    const double complex om = 1.0 / tau;
+    const double complex Fc[3] = {F[0], F[1], F[2]};
+    /* Output map: u^n of every fluid node as a function of f^n and F. */
+    {
+        const double* fn = traj + state * (size_t)nsteps;
+        for (long id = 0; id < N; ++id) {
+            for (int a = 0; a < Q; ++a) lam[id * Q + a] = 0.0;
+            if (!s->geo[id]) continue;
+            double complex fc[ORC_QMAX], r, uN[3];
+            for (int b = 0; b < Q; ++b) {
+                for (int a = 0; a < Q; ++a) fc[a] = fn[id * Q + a];
+                fc[b] = CMPLX(fn[id * Q + b], h);
+                node_moments_c(L, Fc, fc, s->comp, &r, uN);
+                double acc = 0.0;
+                for (int d = 0; d < L->D; ++d) acc = acc + cimag(uN[d]) / h * ubar[d * N + id];
+                lam[id * Q + b] = acc;
+            }
+            for (int a = 0; a < Q; ++a) fc[a] = fn[id * Q + a];
+            for (int d = 0; d < L->D; ++d) {
+                double complex Fp[3] = {F[0], F[1], F[2]};
+                Fp[d] = CMPLX(F[d], h);
+                node_moments_c(L, Fp, fc, s->comp, &r, uN);
+                for (int e = 0; e < L->D; ++e)
+                    Fb[d] = Fb[d] + cimag(uN[e]) / h * ubar[e * N + id];
+            }
         }
-    for (long id = 0; id < N; ++id)
-        if (s->geo[id])
-            for (int d = 0; d < L->D; ++d) Fb[d] = Fb[d] + ubar[d * N + id] / (2.0 * ORC_RHO0);
+    }
 
     for (int k = nsteps - 1; k >= 0; --k) {
         const double* fk = traj + state * (size_t)k;
-        /* S^T: the population that left x along a arrived at x + e_a, or came
-         * back to x as abar when x + e_a is solid. */
+        /* P^T: every population pulled from slot (node, dir) sends its
+         * adjoint back there. */
+        for (size_t i = 0; i < state; ++i) lstar[i] = 0.0;
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
                     long id = node_id(s, x, y, z);
+                    if (!s->geo[id]) continue;
                     for (int a = 0; a < Q; ++a) {
-                        if (!s->geo[id]) {
-                            lstar[id * Q + a] = 0.0;
-                            continue;
-                        }
-                        long dst = neighbour(s, x, y, z, a, +1);
-                        lstar[id * Q + a] =
-                            dst >= 0 ? lam[dst * Q + a] : lam[id * Q + opposite(L, a)];
+                        long node;
+                        int dir;
+                        pull_source(s, x, y, z, a, &node, &dir);
+                        lstar[node * Q + dir] = lstar[node * Q + dir] + lam[id * Q + a];
                     }
                 }
         double tb_step = 0.0, Fb_step[3] = {0.0, 0.0, 0.0};
@@ -662,26 +783,24 @@ int orc_adjoint(int lattice, int nx, int ny, int nz, double tau, const double F[
             }
             const double* ls = lstar + id * Q;
             double complex fc[ORC_QMAX], out[ORC_QMAX];
-            double complex Fc[3] = {F[0], F[1], F[2]};
-            const double complex om = 1.0 / tau;
             /* (dC/df)^T lambda*: column b of dC/df from C(f + i h e_b). */
             for (int b = 0; b < Q; ++b) {
                 for (int a = 0; a < Q; ++a) fc[a] = fk[id * Q + a];
                 fc[b] = CMPLX(fk[id * Q + b], h);
-                node_collide_c(L, om, Fc, fc, out);
+                node_collide_c(L, om, Fc, s->comp, fc, out);
                 double acc = 0.0;
                 for (int a = 0; a < Q; ++a) acc = acc + cimag(out[a]) / h * ls[a];
                 lam[id * Q + b] = acc;
             }
             for (int a = 0; a < Q; ++a) fc[a] = fk[id * Q + a];
             /* (dC/dtau)^T lambda* */
-            node_collide_c(L, 1.0 / CMPLX(tau, h), Fc, fc, out);
+            node_collide_c(L, 1.0 / CMPLX(tau, h), Fc, s->comp, fc, out);
             for (int a = 0; a < Q; ++a) tb_step = tb_step + cimag(out[a]) / h * ls[a];
             /* (dC/dF)^T lambda* */
             for (int d = 0; d < L->D; ++d) {
                 double complex Fp[3] = {F[0], F[1], F[2]};
                 Fp[d] = CMPLX(F[d], h);
-                node_collide_c(L, om, Fp, fc, out);
+                node_collide_c(L, om, Fp, s->comp, fc, out);
                 for (int a = 0; a < Q; ++a) Fb_step[d] = Fb_step[d] + cimag(out[a]) / h * ls[a];
             }
         }
@@ -689,6 +808,20 @@ int orc_adjoint(int lattice, int nx, int ny, int nz, double tau, const double F[
         for (int d = 0; d < 3; ++d) Fb[d] = Fb[d] + Fb_step[d];
     }
 
+    /* B^T: an unknown population of a nodal wall node is a copy of the
+     * opposite one. */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long id = node_id(s, x, y, z);
+                if (!s->geo[id]) continue;
+                for (int a = 0; a < Q; ++a)
+                    if (neighbour(s, x, y, z, a, -1) == ORC_BEYOND) {
+                        const int abar = opposite(L, a);
+                        lam[id * Q + abar] = lam[id * Q + abar] + lam[id * Q + a];
+                        lam[id * Q + a] = 0.0;
+                    }
+            }
     /* Init map: f^0_a = feq_a(rho_init, u0); u0bar = (dfeq/du0)^T lambda^0. */
     for (long id = 0; id < N; ++id) {
         for (int d = 0; d < 3; ++d) u0bar[d * N + id] = 0.0;
@@ -697,7 +830,7 @@ int orc_adjoint(int lattice, int nx, int ny, int nz, double tau, const double F[
             double complex uu[3] = {u0[id], u0[N + id], u0[2 * N + id]};
             double complex feq[ORC_QMAX];
             uu[d] = CMPLX(u0[d * N + id], h);
-            node_equilibrium_c(L, rho0[id], uu, feq);
+            node_equilibrium_c(L, rho0[id], uu, s->comp, feq);
             double acc = 0.0;
             for (int a = 0; a < Q; ++a) acc = acc + cimag(feq[a]) / h * lam[id * Q + a];
             u0bar[d * N + id] = acc;

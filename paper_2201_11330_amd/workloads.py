@@ -16,7 +16,7 @@ import math
 import numpy as np
 
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
-PERIODIC, SOLID_ENDS, WALLS_OUTSIDE = 0, 1, 2
+PERIODIC, SOLID_ENDS, WALLS_OUTSIDE, WALLS_NODAL = 0, 1, 2, 3
 Q_OF = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 
 

@@ -468,18 +468,25 @@ def test_adjoint_closed_form_mean_velocity():
     assert abs(taubar) < 1e-10
 
 
-@pytest.mark.parametrize("lattice,dims,bc", [
-    (oracle.D2Q9, (6, 7, 1), (0, 0, 0)),
-    (oracle.D2Q9, (5, 8, 1), (0, 1, 0)),
-    (oracle.D3Q19, (4, 6, 5), (0, 1, 0)),
-    (oracle.D3Q19, (5, 4, 4), (2, 0, 1)),
-    (oracle.D3Q27, (4, 5, 4), (0, 1, 2)),
+@pytest.mark.parametrize("lattice,dims,bc,opts", [
+    (oracle.D2Q9, (6, 7, 1), (0, 0, 0), {}),
+    (oracle.D2Q9, (5, 8, 1), (0, 1, 0), {}),
+    (oracle.D3Q19, (4, 6, 5), (0, 1, 0), {}),
+    (oracle.D3Q19, (5, 4, 4), (2, 0, 1), {}),
+    (oracle.D3Q27, (4, 5, 4), (0, 1, 2), {}),
+    (oracle.D2Q9, (6, 7, 1), (0, 0, 0), {"compressible": True}),
+    (oracle.D3Q19, (5, 6, 4), (0, 1, 2), {"compressible": True}),
+    (oracle.D2Q9, (5, 7, 1), (0, 3, 0), {}),
+    (oracle.D3Q19, (4, 5, 6), (2, 0, 3), {}),
+    (oracle.D3Q27, (5, 4, 4), (3, 1, 0), {"compressible": True}),
+    (oracle.D3Q19, (7, 6, 5), (0, 3, 0), {"solid": "box"}),
 ])
-def test_adjoint_matches_complex_step_tangent(lattice, dims, bc):
+def test_adjoint_matches_complex_step_tangent(lattice, dims, bc, opts):
     """Pin P13: the transposed run (complex-step Jacobians of each collision,
-    inverse propagation) and the complex-step tangent of the whole forward run
-    give the same directional derivative of J = 1/2 |u^N - u_tgt|^2 along
-    random directions in (u0, tau, F)."""
+    transposed propagation) and the complex-step tangent of the whole forward
+    run give the same directional derivative of J = 1/2 |u^N - u_tgt|^2 along
+    random directions in (u0, tau, F); for both equilibria, halfway and nodal
+    walls and a solid mask."""
     nx, ny, nz = dims
     D = 2 if lattice == oracle.D2Q9 else 3
     rng = np.random.default_rng(7)
@@ -493,14 +500,20 @@ def test_adjoint_matches_complex_step_tangent(lattice, dims, bc):
     Q = {oracle.D2Q9: 9, oracle.D3Q19: 19, oracle.D3Q27: 27}[lattice]
     noise = 1e-4 * rng.standard_normal((Q, nz, ny, nx))
     tau, N = 0.8, 9
-    s = oracle.Sim(lattice, *dims, tau=tau, force=F, bc=bc)
+    comp = opts.get("compressible", False)
+    solid = _box_mask(dims, (2, 2, 1), (4, 3, 3)) if opts.get("solid") else None
+    s = oracle.Sim(lattice, *dims, tau=tau, force=F, bc=bc, compressible=comp)
+    if solid is not None:
+        s.set_solid(solid)
     s.init_equilibrium(rho, u0, noise)
     s.step(N)
     _, uN = s.moments()
     fluid = s.geometry()
+    u_tgt *= fluid
     ubar = (uN - u_tgt) * fluid
     ubar[D:] = 0.0
-    u0bar, taubar, Fbar = oracle.adjoint(lattice, dims, tau, F, bc, rho, u0, ubar, N, noise)
+    u0bar, taubar, Fbar = oracle.adjoint(lattice, dims, tau, F, bc, rho, u0, ubar, N, noise,
+                                         solid=solid, compressible=comp)
     for trial in range(3):
         du0 = np.zeros_like(u0)
         du0[:D] = rng.standard_normal((D, nz, ny, nx))
@@ -508,7 +521,8 @@ def test_adjoint_matches_complex_step_tangent(lattice, dims, bc):
         dF = np.zeros(3)
         dF[:D] = rng.standard_normal(D)
         J, dJ = oracle.cs_objective(lattice, dims, tau, F, bc, rho, u0, u_tgt, N, dtau=dtau,
-                                    dforce=dF, du0=du0, noise=noise)
+                                    dforce=dF, du0=du0, noise=noise, solid=solid,
+                                    compressible=comp)
         adj = (u0bar * du0).sum() + taubar * dtau + Fbar @ dF
         assert abs(adj - dJ) <= 1e-12 * abs(dJ), (adj, dJ)
         assert abs(J - 0.5 * (ubar ** 2).sum()) < 1e-14

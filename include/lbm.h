@@ -29,9 +29,15 @@
  *     model's moment (Sec. 2.1) shifted by half the body force F, which
  *     enters the collision as t_a [3 (e_a - u).F + 9 (e_a.u)(e_a.F)] times
  *     (1 - omega/2) (trapezoidal forcing; the paper gives no force term).
+ *     The equilibrium is the incompressible one of Eq. (incompressible_feq),
+ *     t_a [rho + rho0 (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)], unless
+ *     LBM_FLAG_COMPRESSIBLE selects the weakly compressible one of Eq.
+ *     (feq), t_a rho [1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u], with
+ *     u = (sum_a e_a f_a + F/2)/rho.
  *   - Walls are halfway bounce-back (Eq. (bb)): a population whose pull
  *     source x - e_a is solid is replaced by the opposite population of the
- *     same node.  Solid nodes carry no state.
+ *     same node.  Solid nodes carry no state.  LBM_WALLS_NODAL gives the
+ *     modified nodal variant of Sec. 2.2 instead.
  *   - The caller owns every device buffer and the stream (e.g. torch tensors
  *     and torch's current stream); they must outlive their use by the
  *     context.  The library owns the context and a small device scratch for
@@ -82,8 +88,14 @@ typedef enum {
     LBM_PERIODIC = 0,      /* wrap-around, done inside the kernels */
     LBM_SOLID_ENDS = 1,    /* first and last planes are solid nodes; walls
                               lie half a cell inside them */
-    LBM_WALLS_OUTSIDE = 2  /* every plane is fluid; walls lie half a cell
+    LBM_WALLS_OUTSIDE = 2, /* every plane is fluid; walls lie half a cell
                               outside the first and last planes */
+    LBM_WALLS_NODAL = 3    /* modified nodal bounce-back (Sec. 2.2): the first
+                              and last planes are wall nodes that collide like
+                              the bulk; after each propagation a population of
+                              a wall node whose source lies beyond the wall is
+                              a copy of the opposite one (Eq. (bb)).  One axis
+                              at most; wall force excludes these walls */
 } lbm_axis_bc;
 
 typedef struct {
@@ -92,26 +104,31 @@ typedef struct {
 
 /* lbm_create flags. */
 enum {
-    LBM_FLAG_AA = 1,   /* in-place AA pattern: one population buffer instead of two */
-    LBM_FLAG_GRAPH = 2 /* lbm_step replays a HIP graph of 32 captured steps (captured on
-                          first use on a private stream, launched on the bound stream):
-                          fewer launch round trips for small, launch-bound boxes */
+    LBM_FLAG_AA = 1,           /* in-place AA pattern: one population buffer instead of two */
+    LBM_FLAG_GRAPH = 2,        /* lbm_step replays a HIP graph of 32 captured steps (captured
+                                  on first use on a private stream, launched on the bound
+                                  stream): fewer launch round trips for small, launch-bound
+                                  boxes */
+    LBM_FLAG_COMPRESSIBLE = 4  /* weakly compressible equilibrium of Eq. (feq), u = j/rho */
 };
 
 /*
  * Creates a context for an nx*ny*nz box.  Checks (LBM_EINVAL otherwise):
  * tau > 1/2 (tau = +inf is pure streaming, allowed only with F = 0);
- * every dimension >= 1 and >= 3 on an LBM_SOLID_ENDS axis; D2Q9 needs
- * nz = 1, a periodic z axis and F_z = 0; F finite; N = nx*ny*nz < 2^31;
- * flags only LBM_FLAG_AA and LBM_FLAG_GRAPH.  force may be NULL (no force); bc may be NULL
- * (fully periodic).  No device work happens here.
+ * every dimension >= 1 and >= 3 on an LBM_SOLID_ENDS or LBM_WALLS_NODAL
+ * axis; LBM_WALLS_NODAL on one axis at most; D2Q9 needs nz = 1, a periodic
+ * z axis and F_z = 0; F finite; N = nx*ny*nz < 2^31; flags only
+ * LBM_FLAG_AA, LBM_FLAG_GRAPH and LBM_FLAG_COMPRESSIBLE.  force may be NULL
+ * (no force); bc may be NULL (fully periodic).  No device work happens
+ * here.
  */
 lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz, double tau,
                       const double force[3], const lbm_bc* bc, lbm_storage storage,
                       unsigned flags);
 
-/* Bytes of one population buffer: Q planes of N nodes (each plane padded to
- * a multiple of 128 elements) of the storage element; a multiple of 256. */
+/* Bytes of one population buffer: the nodes in tiles of T = 4096 (fewer,
+ * a power of two, for boxes under 4096 nodes), Q runs of T storage elements
+ * per tile, whole tiles; a multiple of 256. */
 size_t lbm_buffer_bytes(const lbm_ctx* ctx);
 
 /*
@@ -126,9 +143,11 @@ lbm_status lbm_bind(lbm_ctx* ctx, void* buf_a, void* buf_b, void* hip_stream);
 
 /*
  * InitPDF: f_a = t_a [rho + rho0 (3 e_a.u + 4.5 (e_a.u)^2 - 1.5 u.u)]
- * (Eq. (incompressible_feq)) on every fluid node, plus noise_a if noise is
- * not NULL.  rho [N], u [3][N], noise [Q][N]: device FP64 fields.
- * Asynchronous on the bound stream.
+ * (Eq. (incompressible_feq); with LBM_FLAG_COMPRESSIBLE the rho0 factor is
+ * rho, Eq. (feq)) on every fluid node, plus noise_a if noise is not NULL.
+ * On nodal wall nodes Eq. (bb) then replaces the unknown populations.
+ * rho [N], u [3][N], noise [Q][N]: device FP64 fields.  Asynchronous on the
+ * bound stream.
  */
 lbm_status lbm_init_equilibrium(lbm_ctx* ctx, const double* rho, const double* u,
                                 const double* noise);
@@ -137,7 +156,10 @@ lbm_status lbm_init_equilibrium(lbm_ctx* ctx, const double* rho, const double* u
  * Sets / reads the populations f^n of the paper's f array after the last
  * Propagation (device FP64 field [Q][N]; solid nodes are ignored on set and
  * read back as 0).  For the FP64 storage the round trip is bit-exact; the
- * other storages round f - t_a on set.  Asynchronous on the bound stream.
+ * other storages round f - t_a on set.  On nodal wall nodes the unknown
+ * populations are determined by Eq. (bb): the values set for them are
+ * ignored and read back as the opposite populations.  Asynchronous on the
+ * bound stream.
  */
 lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f);
 lbm_status lbm_get_populations(lbm_ctx* ctx, double* f);
@@ -147,15 +169,17 @@ lbm_status lbm_step(lbm_ctx* ctx, int n);
 
 /*
  * PostProcessing of the current f^n: rho = sum_a f_a [N] and
- * u = (sum_a e_a f_a + F/2)/rho0 [3][N], written as FP64 (out_is_f32 = 0) or
+ * u = (sum_a e_a f_a + F/2)/rho0 [3][N] (divided by rho instead with
+ * LBM_FLAG_COMPRESSIBLE), written as FP64 (out_is_f32 = 0) or
  * FP32 (out_is_f32 = 1) device fields; either pointer may be NULL.  Solid
  * nodes read 0.  Asynchronous on the bound stream.
  */
 lbm_status lbm_moments(lbm_ctx* ctx, void* rho, void* u, int out_is_f32);
 
 /*
- * Monitor: total mass sum rho, kinetic energy (rho0/2) sum |u|^2 and
- * max |u| over the fluid nodes, accumulated in FP64 in a fixed order (the
+ * Monitor: total mass sum rho, kinetic energy (rho0/2) sum |u|^2 (sum
+ * (rho/2) |u|^2 with LBM_FLAG_COMPRESSIBLE) and max |u| over the fluid
+ * nodes, accumulated in FP64 in a fixed order (the
  * result does not depend on scheduling).  Host outputs, any may be NULL.
  * Synchronises the bound stream.  Returns LBM_EUNSTABLE (outputs still
  * written) when a population is NaN or infinite.
@@ -176,8 +200,9 @@ lbm_status lbm_reduce(lbm_ctx* ctx, double* mass, double* kinetic_energy, double
 lbm_status lbm_set_solid(lbm_ctx* ctx, const unsigned char* solid);
 
 /*
- * Momentum-exchange force on all walls (solid nodes and the box walls)
- * during the last propagation, the drag evaluation of Sec. 4:
+ * Momentum-exchange force on all halfway walls (solid nodes and the box
+ * walls; not LBM_WALLS_NODAL walls) during the last propagation, the drag
+ * evaluation of Sec. 4:
  * F = sum over fluid x and directions a with x + e_a a wall of
  * [f*_a(x, t) + f_abar(x, t + 1)] e_a = 2 f_abar(x, t + 1) e_a (the
  * population that came back is the one that left).  Host output [3],
@@ -195,6 +220,10 @@ long long lbm_steps_taken(const lbm_ctx* ctx);
  * final velocity u^n = sum_a e_a f^n_a + F/2.  For a scalar J(u^n) the
  * adjoint returns dJ/du0, dJ/dtau and dJ/dF given dJ/du^n.
  *
+ * In the compressible model u^n = (sum_a e_a f^n_a + F/2)/rho^n and the
+ * init map's equilibrium carries the factor rho.  With LBM_WALLS_NODAL the
+ * forward step includes the copy of Eq. (bb) on wall nodes.
+ *
  * lbm_forward_record advances n steps from the current state like
  * lbm_step(ctx, n) and stores the state at steps 0, k, 2k, ..., n-k
  * (relative to the start) in ckpt: n/k consecutive device buffers of
@@ -204,7 +233,8 @@ long long lbm_steps_taken(const lbm_ctx* ctx);
 lbm_status lbm_forward_record(lbm_ctx* ctx, int n, int k, void* ckpt);
 
 /* Device workspace lbm_adjoint needs for checkpoint interval k: k-1 state
- * buffers for the recomputed segment, two adjoint fields and the FP64
+ * buffers for the recomputed segment (k with LBM_FLAG_COMPRESSIBLE, whose
+ * output map needs the final state), two adjoint fields and the FP64
  * accumulators.  0 for a NULL context or k < 1. */
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k);
 
@@ -216,6 +246,8 @@ size_t lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k);
  * bounce-back links reversed) and the transposed collision Jacobian.  The
  * segment recompute and the adjoint steps read the stored states; the
  * context's own buffers and state are not touched.
+ *   rho0   [N] device FP64: the density given to lbm_init_equilibrium;
+ *          read with LBM_FLAG_COMPRESSIBLE only (may be NULL otherwise)
  *   u0     [3][N] device FP64: the initial velocity given to
  *          lbm_init_equilibrium (the init map's linearisation point)
  *   dJ_du  [3][N] device FP64: dJ/du^n (solid nodes ignored)
@@ -225,10 +257,12 @@ size_t lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k);
  * work: lbm_adjoint_workspace_bytes(ctx, k) bytes of device memory,
  * 256-byte aligned.  Adjoint fields use the storage's arithmetic type
  * (FP64 for LBM_F64, FP32 otherwise).  Needs a finite tau and the
- * two-lattice pattern.  Synchronises the bound stream.
+ * two-lattice pattern, and n >= 1 with LBM_FLAG_COMPRESSIBLE.
+ * Synchronises the bound stream.
  */
-lbm_status lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, void* work, const double* u0,
-                       const double* dJ_du, double* dJ_du0, double* dJ_dtau, double dJ_dforce[3]);
+lbm_status lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, void* work,
+                       const double* rho0, const double* u0, const double* dJ_du, double* dJ_du0,
+                       double* dJ_dtau, double dJ_dforce[3]);
 
 /* Frees the context and its scratch (not the caller's buffers).  NULL is a
  * no-op. */

@@ -59,6 +59,8 @@ struct lbm_ctx {
     lbm_storage storage;
     unsigned flags;
     bool walls, force, aa;
+    bool comp = false;  // compressible equilibrium (LBM_FLAG_COMPRESSIBLE)
+    int nodal = -1;     // axis with LBM_WALLS_NODAL, or -1
 
     bool bound = false;
     void* buf[2] = {nullptr, nullptr};
@@ -91,8 +93,8 @@ struct Ops {
     lbm_status (*export_f)(lbm_ctx*, double* f);
     lbm_status (*moments)(lbm_ctx*, void* rho, void* u, int f32);
     lbm_status (*reduce)(lbm_ctx*);
-    lbm_status (*adjoint)(lbm_ctx*, int n, int k, const void* ckpt, void* ws, const double* u0,
-                          const double* ubar, double* u0bar, double* out4);
+    lbm_status (*adjoint)(lbm_ctx*, int n, int k, const void* ckpt, void* ws, const double* rho0,
+                          const double* u0, const double* ubar, double* u0bar, double* out4);
     lbm_status (*build_links)(lbm_ctx*, const unsigned char* mask);
     lbm_status (*wall_force)(lbm_ctx*);
     lbm_status (*step_between)(lbm_ctx*, const void* src, void* dst);
@@ -114,6 +116,7 @@ inline Dims dims_of(const lbm_ctx* c)
     g.N = c->N;
     g.S = c->S;
     g.links = c->links;
+    g.nodal = c->nodal;
     return g;
 }
 
@@ -131,6 +134,7 @@ inline IoArgs io_args(const lbm_ctx* c)
     p.g = dims_of(c);
     p.bx_shift = c->bx_shift;
     p.mode = state_mode(c);
+    p.comp = c->comp ? 1 : 0;
     for (int d = 0; d < 3; ++d) p.F[d] = c->F[d];
     return p;
 }
@@ -168,7 +172,8 @@ inline WorkspaceLayout workspace_layout(const lbm_ctx* c, int k)
     L.nblocks = size_t(c->grid.x) * c->grid.y * c->grid.z;
     L.acc_doubles = L.nblocks * kAccSlots;
     L.seg = 0;
-    L.lam0 = L.seg + size_t(k > 1 ? k - 1 : 0) * L.state_bytes;
+    // k-1 recomputed states, and the final state for the compressible seed
+    L.lam0 = L.seg + size_t(k - 1 + (c->comp ? 1 : 0)) * L.state_bytes;
     L.lam1 = L.lam0 + round256(c->state_elems * celem);
     L.acc = L.lam1 + round256(c->state_elems * celem);
     L.result = L.acc + round256(L.acc_doubles * sizeof(double));

@@ -6,24 +6,47 @@
 
 namespace imexlbm {
 
+// Compile-time configuration of the step kernels: walls or masks present,
+// body force, compressible equilibrium (which always takes the force path).
+template <bool W, bool F, bool M>
+struct Cfg {
+    static constexpr bool walls = W, force = F, comp = M;
+};
+
+// Calls fn(Cfg<...>{}) for the context's configuration.
+template <class Fn>
+void dispatch(const lbm_ctx* c, Fn&& fn)
+{
+    if (c->comp) {
+        if (c->walls) fn(Cfg<true, true, true>{});
+        else fn(Cfg<false, true, true>{});
+    } else if (c->walls) {
+        if (c->force) fn(Cfg<true, true, false>{});
+        else fn(Cfg<true, false, false>{});
+    } else {
+        if (c->force) fn(Cfg<false, true, false>{});
+        else fn(Cfg<false, false, false>{});
+    }
+}
+
 // Kernel instantiations of one lattice and storage.
 template <int L, class S>
 struct Impl {
-    template <bool W, bool F>
+    template <class K>
     static void step_ab(lbm_ctx* c, const S* src, S* dst)
     {
-        hipLaunchKernelGGL((k_step_ab<L, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, src, dst,
-                           step_args<typename Store<S>::C>(c));
+        hipLaunchKernelGGL((k_step_ab<L, S, K::walls, K::force, K::comp, kNtStores>), c->grid, c->block, 0,
+                           c->stream, src, dst, step_args<typename Store<S>::C>(c));
     }
-    template <bool W, bool F>
+    template <class K>
     static void step_aa(lbm_ctx* c, S* A, bool odd)
     {
         if (odd)
-            hipLaunchKernelGGL((k_step_aa_odd<L, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, A,
-                               step_args<typename Store<S>::C>(c));
+            hipLaunchKernelGGL((k_step_aa_odd<L, S, K::walls, K::force, K::comp, kNtStores>), c->grid,
+                               c->block, 0, c->stream, A, step_args<typename Store<S>::C>(c));
         else
-            hipLaunchKernelGGL((k_step_aa_even<L, S, W, F, kNtStores>), c->grid, c->block, 0, c->stream, A,
-                               step_args<typename Store<S>::C>(c));
+            hipLaunchKernelGGL((k_step_aa_even<L, S, K::walls, K::force, K::comp, kNtStores>), c->grid,
+                               c->block, 0, c->stream, A, step_args<typename Store<S>::C>(c));
     }
 
     // Captures kGraphSteps steps starting from an even step count (buffer 0
@@ -86,17 +109,11 @@ struct Impl {
             if (c->aa) {
                 S* A = static_cast<S*>(c->buf[0]);
                 const bool odd = c->steps & 1;
-                if (c->walls)
-                    c->force ? step_aa<true, true>(c, A, odd) : step_aa<true, false>(c, A, odd);
-                else
-                    c->force ? step_aa<false, true>(c, A, odd) : step_aa<false, false>(c, A, odd);
+                dispatch(c, [&](auto k) { step_aa<decltype(k)>(c, A, odd); });
             } else {
                 const S* src = static_cast<const S*>(c->buf[c->cur]);
                 S* dst = static_cast<S*>(c->buf[1 - c->cur]);
-                if (c->walls)
-                    c->force ? step_ab<true, true>(c, src, dst) : step_ab<true, false>(c, src, dst);
-                else
-                    c->force ? step_ab<false, true>(c, src, dst) : step_ab<false, false>(c, src, dst);
+                dispatch(c, [&](auto k) { step_ab<decltype(k)>(c, src, dst); });
                 c->cur = 1 - c->cur;
             }
             ++c->steps;
@@ -108,10 +125,7 @@ struct Impl {
     // One two-lattice step between explicit buffers.
     static void step_between_t(lbm_ctx* c, const S* src, S* dst)
     {
-        if (c->walls)
-            c->force ? step_ab<true, true>(c, src, dst) : step_ab<true, false>(c, src, dst);
-        else
-            c->force ? step_ab<false, true>(c, src, dst) : step_ab<false, false>(c, src, dst);
+        dispatch(c, [&](auto k) { step_ab<decltype(k)>(c, src, dst); });
     }
 
     using C = typename Store<S>::C;
@@ -127,17 +141,29 @@ struct Impl {
         return p;
     }
 
-    template <bool W, bool F>
+    template <class K>
     static void adj_step(lbm_ctx* c, const S* g, const C* lin, C* lout, double* acc)
     {
-        hipLaunchKernelGGL((k_adjoint_step<L, S, W, F>), c->grid, c->block, 0, c->stream, g, lin, lout,
-                           acc, adj_args(c));
+        hipLaunchKernelGGL((k_adjoint_step<L, S, K::walls, K::force, K::comp>), c->grid, c->block, 0,
+                           c->stream, g, lin, lout, acc, adj_args(c));
+    }
+
+    // Transpose of Eq. (bb) on nodal walls, applied to an adjoint field.
+    static void nodal_bt(lbm_ctx* c, C* lam)
+    {
+        if (c->nodal < 0) return;
+        const int n[3] = {c->nx, c->ny, c->nz};
+        const int u = c->nodal == 0 ? 1 : 0, v = c->nodal == 2 ? 1 : 2;
+        const size_t work = 2 * size_t(n[u]) * size_t(n[v]);
+        hipLaunchKernelGGL((k_adjoint_nodal_bt<L, C>), dim3(unsigned((work + 255) / 256)), dim3(256), 0,
+                           c->stream, lam, dims_of(c));
     }
 
     // Backward sweep over n steps with checkpoints every k steps; see
-    // lbm_adjoint.  ws holds (k-1) state buffers, two lambda fields and the
+    // lbm_adjoint.  ws holds the recomputed segment (k-1 states, plus the
+    // final state in the compressible model), two lambda fields and the
     // per-workgroup accumulators.
-    static lbm_status adjoint(lbm_ctx* c, int n, int k, const void* ckpt, void* ws,
+    static lbm_status adjoint(lbm_ctx* c, int n, int k, const void* ckpt, void* ws, const double* rho0,
                               const double* u0, const double* ubar, double* u0bar, double* out4)
     {
         const WorkspaceLayout W = workspace_layout(c, k);
@@ -146,39 +172,45 @@ struct Impl {
         double* acc = reinterpret_cast<double*>(w + W.acc);
         double* result = reinterpret_cast<double*>(w + W.result);
         const Dims g = dims_of(c);
+        IoArgs io = io_args(c);
+        io.mode = kPull;
         hipLaunchKernelGGL(k_fill_zero, dim3((W.acc_doubles + 255) / 256), dim3(256), 0, c->stream, acc,
                            W.acc_doubles);
-        if (c->walls)
-            hipLaunchKernelGGL((k_adjoint_seed<L, S, true>), c->grid, c->block, 0, c->stream, ubar, lam[0],
-                               acc, g, c->bx_shift);
-        else
-            hipLaunchKernelGGL((k_adjoint_seed<L, S, false>), c->grid, c->block, 0, c->stream, ubar, lam[0],
-                               acc, g, c->bx_shift);
+        // Output map; the compressible one needs the final state, the step
+        // after the last recomputed state of the last segment.
+        auto seed = [&](const S* fN) {
+            dispatch(c, [&](auto cfg) {
+                using K = decltype(cfg);
+                hipLaunchKernelGGL((k_adjoint_seed<L, S, K::walls, K::comp>), c->grid, c->block, 0, c->stream,
+                                   ubar, fN, lam[0], acc, io);
+            });
+        };
+        if (!c->comp) seed(nullptr);
         int cur = 0;
         const char* ck = static_cast<const char*>(ckpt);
         for (int s = n / k - 1; s >= 0; --s) {
             const S* state0 = reinterpret_cast<const S*>(ck + size_t(s) * W.state_bytes);
-            auto state = [&](int j) -> const S* {
-                return j == 0 ? state0 : reinterpret_cast<const S*>(w + W.seg + size_t(j - 1) * W.state_bytes);
+            auto state = [&](int j) -> S* {
+                return j == 0 ? const_cast<S*>(state0)
+                              : reinterpret_cast<S*>(w + W.seg + size_t(j - 1) * W.state_bytes);
             };
-            for (int j = 1; j < k; ++j)
-                step_between_t(c, state(j - 1), const_cast<S*>(state(j)));
+            for (int j = 1; j < k; ++j) step_between_t(c, state(j - 1), state(j));
+            if (c->comp && s == n / k - 1) {
+                step_between_t(c, state(k - 1), state(k));
+                seed(state(k));
+            }
             for (int j = k - 1; j >= 0; --j) {
-                if (c->walls)
-                    c->force ? adj_step<true, true>(c, state(j), lam[cur], lam[1 - cur], acc)
-                             : adj_step<true, false>(c, state(j), lam[cur], lam[1 - cur], acc);
-                else
-                    c->force ? adj_step<false, true>(c, state(j), lam[cur], lam[1 - cur], acc)
-                             : adj_step<false, false>(c, state(j), lam[cur], lam[1 - cur], acc);
+                nodal_bt(c, lam[cur]);
+                dispatch(c, [&](auto cfg) { adj_step<decltype(cfg)>(c, state(j), lam[cur], lam[1 - cur], acc); });
                 cur = 1 - cur;
             }
         }
-        if (c->walls)
-            hipLaunchKernelGGL((k_adjoint_init_map<L, S, true>), c->grid, c->block, 0, c->stream, lam[cur], u0,
-                               u0bar, g, c->bx_shift);
-        else
-            hipLaunchKernelGGL((k_adjoint_init_map<L, S, false>), c->grid, c->block, 0, c->stream, lam[cur], u0,
-                               u0bar, g, c->bx_shift);
+        nodal_bt(c, lam[cur]);
+        dispatch(c, [&](auto cfg) {
+            using K = decltype(cfg);
+            hipLaunchKernelGGL((k_adjoint_init_map<L, S, K::walls, K::comp>), c->grid, c->block, 0, c->stream,
+                               lam[cur], rho0, u0, u0bar, g, c->bx_shift);
+        });
         hipLaunchKernelGGL(k_adjoint_sum, dim3(1), dim3(256), 0, c->stream, acc, W.nblocks, result);
         LBM_HIP(hipGetLastError());
         LBM_HIP(hipMemcpyAsync(out4, result, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -21,6 +21,12 @@
 // writing f*_a to slot abar; odd steps read the neighbours' opposite slots
 // and write back to where the next even step finds them.  A work-item
 // reads and writes the same set of addresses, so the update is in place.
+//
+// Walls of the modified nodal scheme (Sec. 2.2) are addressed like walls
+// half a cell outside the box; after the loads, the populations of a wall
+// node whose source lies beyond the wall are replaced by the opposite ones
+// (Eq. (bb)) before the collision, so the slots they were read from carry
+// nothing (nodal_fill).
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -34,7 +40,7 @@
 
 namespace imexlbm {
 
-enum AxisBC : int { kPeriodic = 0, kSolidEnds = 1, kWallsOutside = 2 };
+enum AxisBC : int { kPeriodic = 0, kSolidEnds = 1, kWallsOutside = 2, kWallsNodal = 3 };
 
 // How a stored state maps to the paper's post-propagation f^n.
 enum GatherMode : int {
@@ -119,6 +125,7 @@ struct Dims {
     // when the pull source x - e_a is a wall (solid node or outside the
     // box), bit 31 when the node itself is solid.
     const unsigned* links;
+    int nodal;  // axis with walls of the modified nodal scheme, or -1
 };
 
 __device__ __forceinline__ unsigned node_index(const Dims& g, int x, int y, int z)
@@ -141,6 +148,7 @@ struct Axis3 {
     bool wall[3];
 };
 
+// A nodal-wall axis is addressed like walls outside the box.
 template <bool WALLS>
 __device__ __forceinline__ Axis3 axis3(int c, int n, int bc)
 {
@@ -236,6 +244,40 @@ __device__ __forceinline__ size_t gather_offset(int mode, int a, unsigned own, u
     return wall ? slot<Q>(a, own, S) : slot<Q>(abar, src, S);  // kPullFlip
 }
 
+// Eq. (bb) on a wall node of the nodal scheme: each population whose pull
+// source lies beyond the wall (e along the nodal axis pointing away from
+// the wall's outside) becomes a copy of the opposite population, which
+// arrived from inside the box.  No-op off the wall planes.
+template <int L, class C>
+__device__ __forceinline__ void nodal_fill(const Dims& g, int x, int y, int z,
+                                           C (&f)[Lattice<L>::Q])
+{
+    const int ax = g.nodal;
+    if (ax < 0) return;
+    const int c = ax == 0 ? x : (ax == 1 ? y : z);
+    const int n = ax == 0 ? g.nx : (ax == 1 ? g.ny : g.nz);
+    const int side = c == 0 ? 1 : (c == n - 1 ? -1 : 0);  // e of the unknowns
+    if (side == 0) return;
+    static_for<Lattice<L>::Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr auto& LT = kLattice<L>;
+        const int e = ax == 0 ? LT.e[a][0] : (ax == 1 ? LT.e[a][1] : LT.e[a][2]);
+        if (e == side) f[a] = f[Lattice<L>::opp(a)];
+    });
+}
+
+// Whether x + sgn e_a lies beyond a wall of the nodal scheme.
+template <int L, int SGN>
+__device__ __forceinline__ bool beyond_nodal(const Dims& g, int x, int y, int z, int a)
+{
+    const int ax = g.nodal;
+    if (ax < 0) return false;
+    const int c = ax == 0 ? x : (ax == 1 ? y : z);
+    const int n = ax == 0 ? g.nx : (ax == 1 ? g.ny : g.nz);
+    const int t = c + SGN * kLattice<L>.e[a][ax];
+    return t < 0 || t >= n;
+}
+
 // Loads and stores of population elements.  NT marks an access
 // non-temporal (streamed, not kept in the caches): used for every store of
 // a step and for the loads whose cache lines no other lane of the workgroup
@@ -279,6 +321,11 @@ __device__ __forceinline__ S get(const S* p)
 //   f*_a = f_a + omega (feq_a - f_a) + (1 - omega/2) w_a (3 (e_a - u).F + 9 (e_a.u)(e_a.F)).
 // The update is affine in f with sum w e = 0, so it maps deviations f - w to
 // deviations unchanged; the reduced-precision storages run it on f - w.
+//
+// COMP selects the weakly compressible equilibrium of Eq. (feq):
+//   u = (sum e f + F/2)/rho,  feq_a = w_a rho (1 + 3 e_a.u + 4.5 (e_a.u)^2 - 1.5 u.u).
+// On deviations (DEV) sum g = rho - 1, and feq_a - w_a =
+// w_a (rho - 1 + rho (3 e_a.u + 4.5 (e_a.u)^2 - 1.5 u.u)).
 
 template <class C>
 struct CollideArgs {
@@ -289,10 +336,11 @@ struct CollideArgs {
 
 template <int L, class C>
 struct Moments {
-    C rho, ux, uy, uz;
+    C rho, ux, uy, uz;  // rho: sum of the stored values (f, or f - w)
+    C rf;               // density rho of the compressible model (COMP only)
 };
 
-template <int L, class C, bool FORCE>
+template <int L, class C, bool FORCE, bool COMP = false, bool DEV = false>
 __device__ __forceinline__ Moments<L, C> node_moments(const C (&f)[Lattice<L>::Q], const C F[3])
 {
     C rho = C(-0.0), jx = C(-0.0), jy = C(-0.0), jz = C(-0.0);
@@ -314,15 +362,23 @@ __device__ __forceinline__ Moments<L, C> node_moments(const C (&f)[Lattice<L>::Q
         m.uy = jy;
         m.uz = kDim<L> == 3 ? jz : C(0);
     }
+    m.rf = C(1);
+    if constexpr (COMP) {
+        m.rf = DEV ? C(1) + rho : rho;
+        const C inv = C(1) / m.rf;
+        m.ux *= inv;
+        m.uy *= inv;
+        m.uz *= inv;
+    }
     return m;
 }
 
-template <int L, class C, bool FORCE>
+template <int L, class C, bool FORCE, bool COMP = false, bool DEV = false>
 __device__ __forceinline__ void collide(C (&f)[Lattice<L>::Q], const CollideArgs<C>& p)
 {
-    const Moments<L, C> m = node_moments<L, C, FORCE>(f, p.F);
+    const Moments<L, C> m = node_moments<L, C, FORCE, COMP, DEV>(f, p.F);
     const C usq = m.ux * m.ux + m.uy * m.uy + (kDim<L> == 3 ? m.uz * m.uz : C(0));
-    const C base = m.rho - C(1.5) * usq;
+    const C base = m.rho - C(1.5) * (COMP ? m.rf * usq : usq);
     C uF = C(0);
     if constexpr (FORCE) uF = m.ux * p.F[0] + m.uy * p.F[1] + (kDim<L> == 3 ? m.uz * p.F[2] : C(0));
     static_for<Lattice<L>::Q>([&](auto ac) {
@@ -330,7 +386,7 @@ __device__ __forceinline__ void collide(C (&f)[Lattice<L>::Q], const CollideArgs
         constexpr int ex = kLattice<L>.e[a][0], ey = kLattice<L>.e[a][1], ez = kLattice<L>.e[a][2];
         const C w = C(kLattice<L>.w[a]);
         const C edu = eterm<ex>(m.ux) + eterm<ey>(m.uy) + eterm<ez>(m.uz);
-        const C feq = w * (base + edu * (C(3) + C(4.5) * edu));
+        const C feq = w * (base + (COMP ? m.rf * edu : edu) * (C(3) + C(4.5) * edu));
         C fs = f[a] + p.omega * (feq - f[a]);
         if constexpr (FORCE) {
             const C eF = eterm<ex>(p.F[0]) + eterm<ey>(p.F[1]) + eterm<ez>(p.F[2]);
@@ -351,7 +407,7 @@ struct StepArgs {
 };
 
 // Fused pull-stream + bounce-back + collide (AB).
-template <int L, class S, bool WALLS, bool FORCE, bool NT>
+template <int L, class S, bool WALLS, bool FORCE, bool COMP, bool NT>
 __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restrict__ dst,
                                                  StepArgs<typename Store<S>::C> p)
 {
@@ -373,7 +429,8 @@ __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restri
         const S* ptr = src + ((WALLS && wall[a]) ? slot<Q>(abar, own, TS) : slot<Q>(a, idx[a], TS));
         f[a] = Store<S>::load(get<NT && aligned>(ptr));
     });
-    collide<L, C, FORCE>(f, p.c);
+    if constexpr (WALLS) nodal_fill<L>(p.g, x, y, z, f);
+    collide<L, C, FORCE, COMP, Store<S>::kDeviation>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         put<NT>(dst + slot<Q>(a, own, TS), Store<S>::save(f[a]));
@@ -381,7 +438,7 @@ __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restri
 }
 
 // AA even step: own slots in, opposite own slots out.
-template <int L, class S, bool WALLS, bool FORCE, bool NT>
+template <int L, class S, bool WALLS, bool FORCE, bool COMP, bool NT>
 __global__ LBM_STEP_BOUNDS void k_step_aa_even(S* __restrict__ A,
                                                       StepArgs<typename Store<S>::C> p)
 {
@@ -397,7 +454,8 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_even(S* __restrict__ A,
         constexpr int a = decltype(ac)::value;
         f[a] = Store<S>::load(get<NT>(A + slot<Q>(a, own, TS)));
     });
-    collide<L, C, FORCE>(f, p.c);
+    if constexpr (WALLS) nodal_fill<L>(p.g, x, y, z, f);
+    collide<L, C, FORCE, COMP, Store<S>::kDeviation>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         put<NT>(A + slot<Q>(Lattice<L>::opp(a), own, TS), Store<S>::save(f[a]));
@@ -407,7 +465,7 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_even(S* __restrict__ A,
 // AA odd step: f_a(x) from slot abar of x - e_a (or slot a of x at a wall);
 // f*_a(x) goes to slot a of x + e_a (or slot abar of x at a wall), which is
 // the address read for direction abar.
-template <int L, class S, bool WALLS, bool FORCE, bool NT>
+template <int L, class S, bool WALLS, bool FORCE, bool COMP, bool NT>
 __global__ LBM_STEP_BOUNDS void k_step_aa_odd(S* __restrict__ A,
                                                      StepArgs<typename Store<S>::C> p)
 {
@@ -432,7 +490,8 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_odd(S* __restrict__ A,
         constexpr int a = decltype(ac)::value;
         f[a] = Store<S>::load(get<NT && kLattice<L>.e[a][0] == 0>(A + off[a]));
     });
-    collide<L, C, FORCE>(f, p.c);
+    if constexpr (WALLS) nodal_fill<L>(p.g, x, y, z, f);
+    collide<L, C, FORCE, COMP, Store<S>::kDeviation>(f, p.c);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         put<NT>(A + off[Lattice<L>::opp(a)], Store<S>::save(f[a]));
@@ -448,6 +507,7 @@ struct IoArgs {
     Dims g;
     int bx_shift;
     int mode;  // GatherMode of the stored state
+    int comp;  // compressible model: u = (sum e f + F/2)/rho
     double F[3];
 };
 
@@ -482,7 +542,8 @@ __global__ __launch_bounds__(256) void k_import(S* __restrict__ A, const double*
             constexpr int a = decltype(ac)::value;
             constexpr auto& LT = kLattice<L>;
             const double edu = eterm<LT.e[a][0]>(ux) + eterm<LT.e[a][1]>(uy) + eterm<LT.e[a][2]>(uz);
-            double v = LT.w[a] * (r + (3.0 * edu + 4.5 * edu * edu - 1.5 * usq));
+            const double rq = p.comp ? r : 1.0;
+            double v = LT.w[a] * (r + rq * (3.0 * edu + 4.5 * edu * edu - 1.5 * usq));
             if (noise) v += noise[size_t(a) * N + own];
             fn[a] = v;
         });
@@ -496,7 +557,8 @@ __global__ __launch_bounds__(256) void k_import(S* __restrict__ A, const double*
     });
 }
 
-// Gathers f^n (in the storage's arithmetic type, as stored: f or f - w).
+// Gathers f^n (in the storage's arithmetic type, as stored: f or f - w),
+// with Eq. (bb) applied on nodal wall nodes.
 template <int L, class S, bool WALLS>
 __device__ __forceinline__ void gather_node(const S* __restrict__ A, const IoArgs& p, int x, int y,
                                             int z, unsigned own,
@@ -510,6 +572,31 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ A, const IoArg
         constexpr int a = decltype(ac)::value;
         f[a] = Store<S>::load(A[gather_offset<L>(p.mode, a, own, idx[a], WALLS && wall[a], p.g.S)]);
     });
+    if constexpr (WALLS) nodal_fill<L>(p.g, x, y, z, f);
+}
+
+// rho, u of f^n as the model defines them, and the sum of the stored values
+// (rho, or rho - 1 for deviation storage), in FP64.
+template <int L, class S>
+__device__ __forceinline__ void node_rho_u(const typename Store<S>::C (&fn)[Lattice<L>::Q],
+                                           const IoArgs& p, double& sum, double& rho,
+                                           double (&u)[3])
+{
+    using C = typename Store<S>::C;
+    const C F[3] = {C(p.F[0]), C(p.F[1]), C(p.F[2])};
+    const Moments<L, C> m = node_moments<L, C, true>(fn, F);
+    sum = double(m.rho);
+    rho = Store<S>::kDeviation ? 1.0 + double(m.rho) : double(m.rho);
+    u[0] = double(m.ux);
+    u[1] = double(m.uy);
+    u[2] = double(m.uz);
+    if (p.comp) {
+        // u = (j + F/2)/rho in the arithmetic type, as the collision forms it
+        const C inv = C(1) / C(Store<S>::kDeviation ? C(1) + m.rho : m.rho);
+        u[0] = double(m.ux * inv);
+        u[1] = double(m.uy * inv);
+        u[2] = double(m.uz * inv);
+    }
 }
 
 template <int L, class S, bool WALLS>
@@ -536,7 +623,7 @@ __global__ __launch_bounds__(256) void k_export(const S* __restrict__ A, double*
 }
 
 // PostProcessing: rho = sum f (= 1 + sum (f - w) for deviation storage),
-// u = sum e f + F/2.
+// u = sum e f + F/2 (divided by rho in the compressible model).
 template <int L, class S, bool WALLS, class O>
 __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ A, O* __restrict__ rho,
                                                  O* __restrict__ u, IoArgs p)
@@ -554,18 +641,19 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ A, O* __r
     }
     C fn[Q];
     gather_node<L, S, WALLS>(A, p, x, y, z, own, fn);
-    const C F[3] = {C(p.F[0]), C(p.F[1]), C(p.F[2])};
-    const Moments<L, C> m = node_moments<L, C, true>(fn, F);
-    if (rho) rho[own] = O(Store<S>::kDeviation ? 1.0 + double(m.rho) : double(m.rho));
+    double sum, r, v[3];
+    node_rho_u<L, S>(fn, p, sum, r, v);
+    if (rho) rho[own] = O(r);
     if (u) {
-        u[own] = O(m.ux);
-        u[size_t(N) + own] = O(m.uy);
-        u[2 * size_t(N) + own] = O(m.uz);
+        u[own] = O(v[0]);
+        u[size_t(N) + own] = O(v[1]);
+        u[2 * size_t(N) + own] = O(v[2]);
     }
 }
 
-// Monitor: per-block FP64 partials (sum rho - rho_ref, sum |u|^2, max |u|,
-// non-finite count) over a fixed grid-stride assignment and a fixed
+// Monitor: per-block FP64 partials (sum rho - rho_ref, sum rho_m |u|^2,
+// max |u|, non-finite count; rho_m = 1 in the incompressible model, rho in
+// the compressible one) over a fixed grid-stride assignment and a fixed
 // in-block tree, so the result is independent of scheduling.
 constexpr int kReduceThreads = 256;
 constexpr int kReduceBlocks = 1024;
@@ -581,7 +669,6 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const S* __r
         s_bad[kReduceThreads], s_cnt[kReduceThreads];
     double mass = 0.0, ke = 0.0, umax = 0.0, bad = 0.0, cnt = 0.0;
     const unsigned N = p.g.N;
-    const C F[3] = {C(p.F[0]), C(p.F[1]), C(p.F[2])};
     for (unsigned n = blockIdx.x * kReduceThreads + threadIdx.x; n < N;
          n += kReduceBlocks * kReduceThreads) {
         const int x = int(n % unsigned(p.g.nx));
@@ -593,11 +680,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const S* __r
         gather_node<L, S, WALLS>(A, p, x, y, z, n, fn);
         for (int a = 0; a < Q; ++a)
             if (!isfinite(double(fn[a]))) bad += 1.0;
-        const Moments<L, C> m = node_moments<L, C, true>(fn, F);
-        const double ux = m.ux, uy = m.uy, uz = m.uz;
-        const double u2 = ux * ux + uy * uy + uz * uz;
-        mass += double(m.rho);
-        ke += u2;
+        double sum, r, v[3];
+        node_rho_u<L, S>(fn, p, sum, r, v);
+        const double u2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        mass += sum;
+        ke += p.comp ? r * u2 : u2;
         umax = fmax(umax, sqrt(u2));
         cnt += 1.0;
     }
@@ -630,7 +717,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const S* __r
 
 // Sums the block partials in block order with one block; out[0..3] = mass
 // (plus the fluid-node count for deviation storage), kinetic energy
-// (rho0/2) sum |u|^2, max |u|, non-finite count.
+// (1/2) sum rho_m |u|^2, max |u|, non-finite count.
 static __global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partials,
                                                                  int nblocks, int deviation,
                                                                  double* __restrict__ out)
@@ -714,8 +801,9 @@ __global__ __launch_bounds__(256) void k_build_links(const unsigned char* __rest
 // Momentum exchanged with the walls in the last propagation (the drag
 // evaluation of Sec. 4): for each fluid node x and direction a whose
 // neighbour x + e_a is a wall, the population that left along a came back
-// as f^n_abar(x), so the wall received 2 f^n_abar(x) e_a.  Per-block FP64
-// partials over a fixed grid-stride assignment (slots 0..2 of 5).
+// as f^n_abar(x), so the wall received 2 f^n_abar(x) e_a.  Links that cross
+// a wall of the nodal scheme are not counted.  Per-block FP64 partials over
+// a fixed grid-stride assignment (slots 0..2 of 5).
 template <int L, class S>
 __global__ __launch_bounds__(kReduceThreads) void k_wall_force(const S* __restrict__ A,
                                                                double* __restrict__ partials,
@@ -736,6 +824,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_wall_force(const S* __restri
         unsigned idx[Q];
         bool out[Q];
         link_nodes<L, true, +1>(p.g, x, y, z, idx, out);
+        for (int a = 0; a < Q; ++a) out[a] = out[a] && !beyond_nodal<L, +1>(p.g, x, y, z, a);
         bool any = false;
         for (int a = 0; a < Q; ++a) any = any || out[a];
         if (!any) continue;

@@ -107,7 +107,8 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
     if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19 && lattice != LBM_D3Q27)
         return fail(LBM_EINVAL, "unknown lattice %d", int(lattice));
     if (storage_size(storage) == 0) return fail(LBM_EINVAL, "unknown storage %d", int(storage));
-    if (flags & ~unsigned(LBM_FLAG_AA | LBM_FLAG_GRAPH)) return fail(LBM_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~unsigned(LBM_FLAG_AA | LBM_FLAG_GRAPH | LBM_FLAG_COMPRESSIBLE))
+        return fail(LBM_EINVAL, "unknown flags 0x%x", flags);
     const int n[3] = {nx, ny, nz};
     int b[3] = {LBM_PERIODIC, LBM_PERIODIC, LBM_PERIODIC};
     if (bc)
@@ -115,12 +116,18 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
     double F[3] = {0.0, 0.0, 0.0};
     if (force)
         for (int d = 0; d < 3; ++d) F[d] = force[d];
+    int nodal = -1;
     for (int d = 0; d < 3; ++d) {
         if (n[d] < 1 || n[d] > 65535) return fail(LBM_EINVAL, "dimension %d = %d outside [1, 65535]", d, n[d]);
-        if (b[d] != LBM_PERIODIC && b[d] != LBM_SOLID_ENDS && b[d] != LBM_WALLS_OUTSIDE)
+        if (b[d] != LBM_PERIODIC && b[d] != LBM_SOLID_ENDS && b[d] != LBM_WALLS_OUTSIDE &&
+            b[d] != LBM_WALLS_NODAL)
             return fail(LBM_EINVAL, "unknown boundary %d on axis %d", b[d], d);
-        if (b[d] == LBM_SOLID_ENDS && n[d] < 3)
-            return fail(LBM_EINVAL, "axis %d has solid ends and needs >= 3 nodes", d);
+        if ((b[d] == LBM_SOLID_ENDS || b[d] == LBM_WALLS_NODAL) && n[d] < 3)
+            return fail(LBM_EINVAL, "axis %d has solid ends or nodal walls and needs >= 3 nodes", d);
+        if (b[d] == LBM_WALLS_NODAL) {
+            if (nodal >= 0) return fail(LBM_EINVAL, "nodal walls on more than one axis");
+            nodal = d;
+        }
         if (!std::isfinite(F[d])) return fail(LBM_EINVAL, "force component %d is not finite", d);
     }
     if (lattice == LBM_D2Q9 && (nz != 1 || b[2] != LBM_PERIODIC || F[2] != 0.0))
@@ -159,6 +166,8 @@ lbm_status lbm_create(lbm_ctx** out, lbm_lattice lattice, int nx, int ny, int nz
     c->use_graph = flags & LBM_FLAG_GRAPH;
     c->walls = b[0] != LBM_PERIODIC || b[1] != LBM_PERIODIC || b[2] != LBM_PERIODIC;
     c->force = has_force;
+    c->comp = flags & LBM_FLAG_COMPRESSIBLE;
+    c->nodal = nodal;
     plan_launch(c);
     *out = c;
     return LBM_OK;
@@ -322,14 +331,17 @@ size_t lbm_adjoint_workspace_bytes(const lbm_ctx* c, int k)
     return workspace_layout(c, k).total;
 }
 
-lbm_status lbm_adjoint(lbm_ctx* c, int n, int k, const void* ckpt, void* work, const double* u0,
-                       const double* dJ_du, double* dJ_du0, double* dJ_dtau, double dJ_dforce[3])
+lbm_status lbm_adjoint(lbm_ctx* c, int n, int k, const void* ckpt, void* work, const double* rho0,
+                       const double* u0, const double* dJ_du, double* dJ_du0, double* dJ_dtau,
+                       double dJ_dforce[3])
 {
     lbm_status st = need_bound(c);
     if (st) return st;
     if (c->aa) return fail(LBM_EINVAL, "the adjoint needs the two-lattice pattern (no LBM_FLAG_AA)");
     if (n < 0 || k < 1 || n % k != 0) return fail(LBM_EINVAL, "need n >= 0, k >= 1 and k dividing n (n=%d k=%d)", n, k);
     if (std::isinf(c->tau)) return fail(LBM_EINVAL, "the adjoint needs a finite tau");
+    if (c->comp && n < 1) return fail(LBM_EINVAL, "the compressible adjoint needs n >= 1");
+    if (c->comp && (st = check_device_ptr(rho0, "rho0", false))) return st;
     if (n > 0 && (st = check_device_ptr(ckpt, "ckpt", false))) return st;
     if ((st = check_device_ptr(work, "work", false))) return st;
     if ((st = check_device_ptr(u0, "u0", false))) return st;
@@ -337,7 +349,7 @@ lbm_status lbm_adjoint(lbm_ctx* c, int n, int k, const void* ckpt, void* work, c
     if ((st = check_device_ptr(dJ_du0, "dJ_du0", false))) return st;
     if (reinterpret_cast<uintptr_t>(work) & 255) return fail(LBM_EINVAL, "work must be 256-byte aligned");
     double out[4];
-    if ((st = c->ops->adjoint(c, n, k, ckpt, work, u0, dJ_du, dJ_du0, c->h_result))) return st;
+    if ((st = c->ops->adjoint(c, n, k, ckpt, work, rho0, u0, dJ_du, dJ_du0, c->h_result))) return st;
     for (int i = 0; i < 4; ++i) out[i] = c->h_result[i];
     if (dJ_dtau) *dJ_dtau = out[0];
     if (dJ_dforce)

@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
 # Enumerations of lbm.h.
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
-PERIODIC, SOLID_ENDS, WALLS_OUTSIDE = 0, 1, 2
+PERIODIC, SOLID_ENDS, WALLS_OUTSIDE, WALLS_NODAL = 0, 1, 2, 3
 F64, F32, F16_DEV, BF16_DEV = 0, 1, 2, 3
-FLAG_AA, FLAG_GRAPH = 1, 2
+FLAG_AA, FLAG_GRAPH, FLAG_COMPRESSIBLE = 1, 2, 4
 OK, EINVAL, ENOTBOUND, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 
 STORAGE_NAMES = {"f64": F64, "f32": F32, "f16": F16_DEV, "bf16": BF16_DEV}
@@ -88,7 +88,7 @@ def lib():
     L.lbm_forward_record.restype = st
     L.lbm_adjoint_workspace_bytes.argtypes = [vp, ctypes.c_int]
     L.lbm_adjoint_workspace_bytes.restype = ctypes.c_size_t
-    L.lbm_adjoint.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, dp, dp]
+    L.lbm_adjoint.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp, dp, dp]
     L.lbm_adjoint.restype = st
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = st
@@ -124,14 +124,17 @@ class LBM:
     """One lattice Boltzmann state on one GPU.
 
     ``tau`` is the lattice relaxation time (omega = 1/tau, nu = (tau - 1/2)/3);
-    ``bc`` gives PERIODIC / SOLID_ENDS / WALLS_OUTSIDE per axis (x, y, z);
-    ``storage`` is "f64", "f32", "f16" or "bf16"; ``aa`` selects the in-place
-    AA pattern; ``graph`` makes step() replay a captured HIP graph of 32 steps.  Launches go to ``stream`` (default: torch's current stream
-    at construction time).
+    ``bc`` gives PERIODIC / SOLID_ENDS / WALLS_OUTSIDE / WALLS_NODAL per axis
+    (x, y, z); ``storage`` is "f64", "f32", "f16" or "bf16"; ``aa`` selects
+    the in-place AA pattern; ``graph`` makes step() replay a captured HIP
+    graph of 32 steps; ``compressible`` selects the equilibrium of Eq. (feq).
+    Launches go to ``stream`` (default: torch's current stream at
+    construction time).
     """
 
     def __init__(self, lattice, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), bc=(0, 0, 0),
-                 storage="f64", aa=False, device=None, stream=None, graph=False):
+                 storage="f64", aa=False, device=None, stream=None, graph=False,
+                 compressible=False):
         L = lib()
         self.lattice = lattice
         self.Q = Q_OF[lattice]
@@ -143,12 +146,14 @@ class LBM:
         self.bc = tuple(int(b) for b in bc)
         self.storage = STORAGE_NAMES[storage] if isinstance(storage, str) else int(storage)
         self.aa = bool(aa)
+        self.compressible = bool(compressible)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         h = ctypes.c_void_p()
         F = (ctypes.c_double * 3)(*self.force)
         bcs = _BC((ctypes.c_int * 3)(*self.bc))
         check(L.lbm_create(ctypes.byref(h), lattice, nx, ny, nz, self.tau, F, ctypes.byref(bcs),
-                           self.storage, (FLAG_AA if self.aa else 0) | (FLAG_GRAPH if graph else 0)),
+                           self.storage, (FLAG_AA if self.aa else 0) | (FLAG_GRAPH if graph else 0)
+                           | (FLAG_COMPRESSIBLE if self.compressible else 0)),
               "lbm_create")
         self._h = h
         nbytes = L.lbm_buffer_bytes(h)
@@ -203,7 +208,8 @@ class LBM:
         return lib().lbm_steps_taken(self._h)
 
     def moments(self, dtype=torch.float64, rho=None, u=None):
-        """(rho, u) of the current state: rho = sum f, u = sum e f + F/2."""
+        """(rho, u) of the current state: rho = sum f, u = sum e f + F/2
+        (over rho in the compressible model)."""
         if rho is None:
             rho = torch.empty(self.shape, dtype=dtype, device=self.device)
         if u is None:
@@ -241,10 +247,12 @@ class LBM:
         check(lib().lbm_forward_record(self._h, int(n), int(k), _ptr(ckpt)), "lbm_forward_record")
         return ckpt
 
-    def adjoint(self, n, k, ckpt, u0, dJ_du, work=None):
+    def adjoint(self, n, k, ckpt, u0, dJ_du, work=None, rho0=None):
         """(dJ/du0 [3,nz,ny,nx] FP64, dJ/dtau, dJ/dF [3]) of a functional of the
-        final velocity, given dJ/du^n; u0 is the velocity the run started from."""
+        final velocity, given dJ/du^n; u0 (and, in the compressible model,
+        rho0) are the fields the run started from."""
         u0 = _dev_f64(u0, (3,) + self.shape, self.device)
+        rho0 = _dev_f64(rho0, self.shape, self.device)
         dJ_du = _dev_f64(dJ_du, (3,) + self.shape, self.device)
         if work is None:
             work = torch.empty(lib().lbm_adjoint_workspace_bytes(self._h, int(k)), dtype=torch.uint8,
@@ -252,8 +260,9 @@ class LBM:
         u0bar = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
         taubar = ctypes.c_double()
         Fbar = (ctypes.c_double * 3)()
-        check(lib().lbm_adjoint(self._h, int(n), int(k), _ptr(ckpt), _ptr(work), _ptr(u0),
-                                _ptr(dJ_du), _ptr(u0bar), ctypes.byref(taubar), Fbar), "lbm_adjoint")
+        check(lib().lbm_adjoint(self._h, int(n), int(k), _ptr(ckpt), _ptr(work), _ptr(rho0),
+                                _ptr(u0), _ptr(dJ_du), _ptr(u0bar), ctypes.byref(taubar), Fbar),
+              "lbm_adjoint")
         return u0bar, taubar.value, [Fbar[0], Fbar[1], Fbar[2]]
 
     def reduce(self):
@@ -274,32 +283,35 @@ class LBMRollout(torch.autograd.Function):
     segment from its checkpoint).
 
     Call as ``LBMRollout.apply(u0, tau, force, rho, n, k, lattice, bc, storage,
-    noise)`` with u0 a [3, nz, ny, nx] FP64 CUDA tensor, tau a scalar tensor,
-    force a 3-vector tensor.  Returns u^n [3, nz, ny, nx] (FP64).
+    noise, compressible)`` with u0 a [3, nz, ny, nx] FP64 CUDA tensor, tau a
+    scalar tensor, force a 3-vector tensor.  Returns u^n [3, nz, ny, nx]
+    (FP64).
     """
 
     @staticmethod
     def forward(ctx, u0, tau, force, rho, n, k, lattice=D3Q19, bc=(0, 0, 0), storage="f64",
-                noise=None):
+                noise=None, compressible=False):
         nz, ny, nx = u0.shape[1:]
         sim = LBM(lattice, nx, ny, nz, float(tau), force=tuple(float(v) for v in force.reshape(-1)),
-                  bc=bc, storage=storage, device=u0.device)
+                  bc=bc, storage=storage, device=u0.device, compressible=compressible)
         u0d = u0.detach().to(torch.float64).contiguous()
-        sim.init_equilibrium(rho, u0d, noise)
+        rhod = _dev_f64(rho, (nz, ny, nx), u0.device)
+        sim.init_equilibrium(rhod, u0d, noise)
         ckpt = sim.forward_record(n, k)
         _, uN = sim.moments()
         ctx.sim, ctx.ckpt, ctx.n, ctx.k = sim, ckpt, n, k
         ctx.tau_like, ctx.force_like = tau, force
-        ctx.save_for_backward(u0d)
+        ctx.save_for_backward(u0d, rhod)
         return uN
 
     @staticmethod
     def backward(ctx, grad_u):
-        (u0d,) = ctx.saved_tensors
-        u0bar, taubar, Fbar = ctx.sim.adjoint(ctx.n, ctx.k, ctx.ckpt, u0d, grad_u.contiguous())
+        u0d, rhod = ctx.saved_tensors
+        u0bar, taubar, Fbar = ctx.sim.adjoint(ctx.n, ctx.k, ctx.ckpt, u0d, grad_u.contiguous(),
+                                              rho0=rhod)
         ctx.sim.close()
         ctx.ckpt = None
         gt = torch.tensor(taubar, dtype=ctx.tau_like.dtype, device=ctx.tau_like.device)
         gF = torch.tensor(Fbar, dtype=ctx.force_like.dtype, device=ctx.force_like.device)
         return (u0bar, gt.reshape(ctx.tau_like.shape), gF.reshape(ctx.force_like.shape),
-                None, None, None, None, None, None, None)
+                None, None, None, None, None, None, None, None)

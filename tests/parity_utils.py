@@ -31,8 +31,9 @@ def inputs(lattice, dims, kind="tg", seed=2, noise_amp=1e-6, bc=(0, 0, 0), U0=0.
     return rho, u, noise
 
 
-def run_oracle(lattice, dims, tau, force, bc, rho, u, noise, steps, solid=None):
-    s = oracle.Sim(lattice, *dims, tau=tau, force=force, bc=bc)
+def run_oracle(lattice, dims, tau, force, bc, rho, u, noise, steps, solid=None,
+               compressible=False):
+    s = oracle.Sim(lattice, *dims, tau=tau, force=force, bc=bc, compressible=compressible)
     if solid is not None:
         s.set_solid(solid)
     s.init_equilibrium(rho, u, noise)
@@ -45,8 +46,9 @@ def run_oracle(lattice, dims, tau, force, bc, rho, u, noise, steps, solid=None):
 
 
 def run_gpu(lattice, dims, tau, force, bc, rho, u, noise, steps, storage="f64", aa=False,
-            reduce=True, solid=None):
-    sim = lbm.LBM(lattice, *dims, tau, force=force, bc=bc, storage=storage, aa=aa)
+            reduce=True, solid=None, compressible=False):
+    sim = lbm.LBM(lattice, *dims, tau, force=force, bc=bc, storage=storage, aa=aa,
+                  compressible=compressible)
     if solid is not None:
         sim.set_solid(solid)
     sim.init_equilibrium(rho, u, noise)

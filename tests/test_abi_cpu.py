@@ -37,7 +37,9 @@ def test_header_enums_match_binding():
                       ("LBM_F32", lbm.F32), ("LBM_F16_DEV", lbm.F16_DEV),
                       ("LBM_BF16_DEV", lbm.BF16_DEV), ("LBM_PERIODIC", lbm.PERIODIC),
                       ("LBM_SOLID_ENDS", lbm.SOLID_ENDS), ("LBM_WALLS_OUTSIDE", lbm.WALLS_OUTSIDE),
+                      ("LBM_WALLS_NODAL", lbm.WALLS_NODAL),
                       ("LBM_FLAG_AA", lbm.FLAG_AA), ("LBM_FLAG_GRAPH", lbm.FLAG_GRAPH),
+                      ("LBM_FLAG_COMPRESSIBLE", lbm.FLAG_COMPRESSIBLE),
                       ("LBM_EINVAL", lbm.EINVAL),
                       ("LBM_ENOTBOUND", lbm.ENOTBOUND), ("LBM_EUNSTABLE", lbm.EUNSTABLE)]:
         m = re.search(rf"\b{name}\s*=\s*(-?\d+)", text)
@@ -59,8 +61,9 @@ def _create(lattice=lbm.D3Q19, nx=8, ny=8, nz=8, tau=0.8, force=None, bc=None, s
     dict(nx=0), dict(ny=-1), dict(nz=70000),
     dict(lattice=lbm.D2Q9, nz=2), dict(lattice=lbm.D2Q9, nz=1, force=(0, 0, 1e-6)),
     dict(lattice=lbm.D2Q9, nz=1, bc=(0, 0, 1)),
-    dict(lattice=7), dict(storage=9), dict(flags=4),
+    dict(lattice=7), dict(storage=9), dict(flags=8),
     dict(bc=(0, 1, 0), ny=2), dict(bc=(5, 0, 0)),
+    dict(bc=(0, 3, 0), ny=2), dict(bc=(3, 3, 0)), dict(bc=(0, 3, 3)),
     dict(force=(float("inf"), 0, 0)), dict(force=(1e-6, 0, 0), tau=math.inf),
     dict(nx=2048, ny=2048, nz=1024),
 ])
@@ -91,6 +94,18 @@ def test_create_accepts_and_sizes():
     st, h = _create(tau=math.inf)  # pure streaming without force is allowed
     assert st == lbm.OK
     L.lbm_destroy(h)
+    # nodal walls on one axis, with other wall kinds; the compressible model
+    for bc in ((0, 3, 0), (1, 3, 2), (3, 0, 1)):
+        st, h = _create(bc=bc, flags=lbm.FLAG_COMPRESSIBLE)
+        assert st == lbm.OK
+        L.lbm_destroy(h)
+    # the compressible adjoint keeps the final state: one more state buffer
+    st, h = _create(flags=lbm.FLAG_COMPRESSIBLE)
+    st2, h2 = _create()
+    assert L.lbm_adjoint_workspace_bytes(h, 3) - L.lbm_adjoint_workspace_bytes(h2, 3) == \
+        L.lbm_buffer_bytes(h)
+    L.lbm_destroy(h)
+    L.lbm_destroy(h2)
     assert L.lbm_destroy(None) == lbm.OK
 
 
@@ -109,7 +124,7 @@ def test_calls_before_bind_fail_without_device_work():
     assert L.lbm_set_solid(h, None) == lbm.ENOTBOUND
     F = (ctypes.c_double * 3)()
     assert L.lbm_wall_force(h, F) == lbm.ENOTBOUND
-    assert L.lbm_adjoint(h, 4, 2, None, None, None, None, None, None, None) == lbm.ENOTBOUND
+    assert L.lbm_adjoint(h, 4, 2, None, None, None, None, None, None, None, None) == lbm.ENOTBOUND
     assert b"lbm_bind" in L.lbm_last_error()
     assert L.lbm_step(None, 1) == lbm.EINVAL
     assert L.lbm_destroy(h) == lbm.OK

@@ -277,6 +277,15 @@ def run_adjoint(n=128, steps=500, k=50, storage="f32", tau=0.7):
     }
 
 
+def step_kernel_name(n, storage, pattern):
+    """The step kernel liblbm launches for this workload: periodic FP64
+    two-lattice boxes with an even nx and at least 2^20 nodes run two nodes
+    per work-item (k_step_ab_pairs), everything else one node."""
+    if pattern == "ab" and storage == "f64" and n % 2 == 0 and n ** 3 >= 1 << 20:
+        return "k_step_ab_pairs<D3Q19,f64>"
+    return f"k_step_{pattern}<D3Q19,{storage}>"
+
+
 def kernel_sources_sha256():
     """Hash of the sources that define the step kernels (device code)."""
     parts = ["paper_2201_11330_amd/csrc/kernels.hpp", "paper_2201_11330_amd/csrc/lattice.hpp"]
@@ -292,7 +301,8 @@ def measured_traffic(storage, pattern, n):
     FETCH_SIZE / WRITE_SIZE figures (scaled by a plain copy of known size),
     or None when no figures exist for this configuration or the kernel
     sources changed since they were taken."""
-    path = os.path.join(ROOT, "profiles", f"k_step_{pattern}_d3q19_{storage}_{n}cube.counters.json")
+    stem = step_kernel_name(n, storage, pattern).split("<")[0]
+    path = os.path.join(ROOT, "profiles", f"{stem}_d3q19_{storage}_{n}cube.counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -378,7 +388,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.storage, args.pattern, n),
-            "kernel": f"k_step_{args.pattern}<D3Q19,{args.storage}>",
+            "kernel": step_kernel_name(n, args.storage, args.pattern),
             "bytes_per_update": blu,
             "launch_ms_mean": round(r["launch_ms_mean"], 5),
         },

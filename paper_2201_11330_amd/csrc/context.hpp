@@ -75,6 +75,10 @@ struct lbm_ctx {
 
     int bx_shift = 8;
     dim3 grid, block;
+    // Periodic FP64 two-lattice steps with two nodes per work-item (even nx).
+    bool pairs = false;
+    int pairs_shift = 7;
+    dim3 pairs_grid;
 
     // LBM_FLAG_GRAPH: kGraphSteps steps captured once, replayed by lbm_step.
     bool use_graph = false;

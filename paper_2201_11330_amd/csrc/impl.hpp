@@ -35,6 +35,13 @@ struct Impl {
     template <class K>
     static void step_ab(lbm_ctx* c, const S* src, S* dst)
     {
+        if constexpr (std::is_same_v<S, double> && !K::walls) {
+            if (c->pairs) {
+                hipLaunchKernelGGL((k_step_ab_pairs<L, K::force, K::comp, kNtStores>), c->pairs_grid, c->block,
+                                   0, c->stream, src, dst, step_args<double>(c), c->pairs_shift);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_step_ab<L, S, K::walls, K::force, K::comp, kNtStores>), c->grid, c->block, 0,
                            c->stream, src, dst, step_args<typename Store<S>::C>(c));
     }

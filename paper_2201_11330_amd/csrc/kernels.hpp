@@ -437,6 +437,98 @@ __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restri
     });
 }
 
+// Fused step of a fully periodic FP64 box with two nodes per work-item
+// (AB).  A work-item owns nodes (x0, x0 + 1), x0 even, and reads every
+// direction as one aligned 16-byte load of the source row at (x0, x0 + 1);
+// a direction with e_x = +1 needs (x0 - 1, x0), so the element x0 - 1 comes
+// from the neighbouring lane by a wave shift (DPP wave_shr:1, a GFX9-family
+// control that gfx950 keeps), and symmetrically e_x = -1 takes x0 + 2 from
+// the next lane (wave_shl:1).  The lane at a wavefront edge or a row end
+// reads that one element itself (periodic wrap).  Same arithmetic per node
+// as k_step_ab; 16-byte accesses measured 3 % faster for FP64 storage on
+// large boxes.  Needs an even nx; lanes per row BXL = 1 << bxl_shift.
+typedef unsigned U32x4 __attribute__((ext_vector_type(4)));
+
+struct Pair {
+    double lo, hi;
+};
+
+template <bool NT>
+__device__ __forceinline__ Pair get_pair(const double* p)
+{
+    const U32x4* q = reinterpret_cast<const U32x4*>(p);
+    if constexpr (NT) return __builtin_bit_cast(Pair, __builtin_nontemporal_load(q));
+    else return __builtin_bit_cast(Pair, *q);
+}
+
+__device__ __forceinline__ void put_pair(double* p, Pair v)
+{
+    __builtin_nontemporal_store(__builtin_bit_cast(U32x4, v), reinterpret_cast<U32x4*>(p));
+}
+
+// Lane i receives v of lane i - 1 (SHIFT = 0x138, wave_shr:1) or of lane
+// i + 1 (SHIFT = 0x130, wave_shl:1); the edge lane keeps its own v.
+template <int SHIFT>
+__device__ __forceinline__ double wave_shift(double v)
+{
+    int2 w = __builtin_bit_cast(int2, v);
+    w.x = __builtin_amdgcn_update_dpp(w.x, w.x, SHIFT, 0xf, 0xf, false);
+    w.y = __builtin_amdgcn_update_dpp(w.y, w.y, SHIFT, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, w);
+}
+
+template <int L, bool FORCE, bool COMP, bool NT>
+__global__ LBM_STEP_BOUNDS void k_step_ab_pairs(const double* __restrict__ src,
+                                                double* __restrict__ dst, StepArgs<double> p,
+                                                int bxl_shift)
+{
+    constexpr int Q = Lattice<L>::Q;
+    const Dims& g = p.g;
+    const int lane = threadIdx.x & 63;
+    const int x0 = ((blockIdx.x << bxl_shift) + int(threadIdx.x & ((1u << bxl_shift) - 1u))) * 2;
+    const int y = blockIdx.y * (256 >> bxl_shift) + int(threadIdx.x >> bxl_shift);
+    const int z = blockIdx.z;
+    // Idle work-items (past the row or the last row) still take part in the
+    // wave shifts; they read row 0 and store nothing.
+    const bool active = x0 < g.nx && y < g.ny;
+    const int xa = active ? x0 : 0, ya = active ? y : 0;
+    const int TS = g.S;
+    double f0[Q], f1[Q];
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr int ex = kLattice<L>.e[a][0], ey = kLattice<L>.e[a][1], ez = kLattice<L>.e[a][2];
+        int ys = ya - ey;
+        ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+        int zs = z - ez;
+        if constexpr (kDim<L> == 3) zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
+        else zs = z;
+        const unsigned row = unsigned(g.nx) * (unsigned(ys) + unsigned(g.ny) * unsigned(zs));
+        const Pair v = get_pair<NT && ex == 0>(src + slot<Q>(a, row + unsigned(xa), TS));
+        if constexpr (ex == 0) {
+            f0[a] = v.lo;
+            f1[a] = v.hi;
+        } else if constexpr (ex == 1) {  // sources x0 - 1, x0
+            double first = wave_shift<0x138>(v.hi);
+            if (lane == 0 || xa == 0) first = src[slot<Q>(a, row + unsigned(xa == 0 ? g.nx - 1 : xa - 1), TS)];
+            f0[a] = first;
+            f1[a] = v.lo;
+        } else {  // sources x0 + 1, x0 + 2
+            double last = wave_shift<0x130>(v.lo);
+            if (lane == 63 || xa + 2 >= g.nx) last = src[slot<Q>(a, row + unsigned(xa + 2 >= g.nx ? 0 : xa + 2), TS)];
+            f0[a] = v.hi;
+            f1[a] = last;
+        }
+    });
+    if (!active) return;
+    collide<L, double, FORCE, COMP, false>(f0, p.c);
+    collide<L, double, FORCE, COMP, false>(f1, p.c);
+    const unsigned own = unsigned(x0) + unsigned(g.nx) * (unsigned(y) + unsigned(g.ny) * unsigned(z));
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        put_pair(dst + slot<Q>(a, own, TS), Pair{f0[a], f1[a]});
+    });
+}
+
 // AA even step: own slots in, opposite own slots out.
 template <int L, class S, bool WALLS, bool FORCE, bool COMP, bool NT>
 __global__ LBM_STEP_BOUNDS void k_step_aa_even(S* __restrict__ A,

@@ -60,6 +60,22 @@ void plan_launch(lbm_ctx* c)
     c->bx_shift = shift;
     c->block = dim3(256, 1, 1);
     c->grid = dim3((c->nx + bx - 1) / bx, (c->ny + by - 1) / by, c->nz);
+
+    // Two nodes per work-item: nx/2 work-items per row.  Only on boxes of at
+    // least 2^20 nodes: a small box is bound by launch latency and runs
+    // faster with twice the workgroups of the one-node kernel.
+    c->pairs = c->storage == LBM_F64 && c->nx % 2 == 0 && c->N >= (1u << 20);
+    if (c->pairs) {
+        const int half = c->nx / 2;
+        int lanes = 1, s2 = 0;
+        while (lanes < half && lanes < 256) {
+            lanes <<= 1;
+            ++s2;
+        }
+        const int rows = 256 / lanes;
+        c->pairs_shift = s2;
+        c->pairs_grid = dim3((half + lanes - 1) / lanes, (c->ny + rows - 1) / rows, c->nz);
+    }
 }
 
 lbm_status need_bound(const lbm_ctx* c)

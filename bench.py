@@ -342,7 +342,20 @@ def cpu_baseline(n, target_s):
         "kind": "oracle",
         "sample": f"D3Q19 {n}^3 FP64 Taylor-Green, {k} whole-domain steps after 1 untimed "
                   f"({dt:.1f} s), AoS paper-order oracle, OpenMP",
+        "cpu_model": host_cpu_model(),
     }
+
+
+def host_cpu_model():
+    """Model name of the host CPU (first entry of /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():

@@ -29,8 +29,9 @@ Q_OF = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 EXPORTS = (
     "lbm_create", "lbm_buffer_bytes", "lbm_bind", "lbm_init_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments", "lbm_reduce",
-    "lbm_steps_taken", "lbm_set_solid", "lbm_wall_force", "lbm_forward_record", "lbm_adjoint_workspace_bytes", "lbm_adjoint",
-    "lbm_destroy", "lbm_status_string", "lbm_last_error",
+    "lbm_steps_taken", "lbm_set_solid", "lbm_wall_force", "lbm_forward_record",
+    "lbm_adjoint_workspace_bytes", "lbm_adjoint", "lbm_destroy", "lbm_status_string",
+    "lbm_last_error",
 )
 
 

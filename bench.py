@@ -279,10 +279,11 @@ def run_adjoint(n=128, steps=500, k=50, storage="f32", tau=0.7):
 
 def step_kernel_name(n, storage, pattern):
     """The step kernel liblbm launches for this workload: periodic FP64
-    two-lattice boxes with an even nx and at least 2^20 nodes run two nodes
-    per work-item (k_step_ab_pairs), everything else one node."""
-    if pattern == "ab" and storage == "f64" and n % 2 == 0 and n ** 3 >= 1 << 20:
-        return "k_step_ab_pairs<D3Q19,f64>"
+    boxes with an even nx and at least 2^20 nodes run two nodes per
+    work-item (k_step_ab_pairs, or k_step_aa_even/odd_pairs), everything
+    else one node."""
+    if storage == "f64" and n % 2 == 0 and n ** 3 >= 1 << 20:
+        return f"k_step_{pattern}_pairs<D3Q19,f64>"
     return f"k_step_{pattern}<D3Q19,{storage}>"
 
 

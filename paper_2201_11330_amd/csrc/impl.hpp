@@ -48,6 +48,17 @@ struct Impl {
     template <class K>
     static void step_aa(lbm_ctx* c, S* A, bool odd)
     {
+        if constexpr (std::is_same_v<S, double> && !K::walls) {
+            if (c->pairs) {
+                if (odd)
+                    hipLaunchKernelGGL((k_step_aa_odd_pairs<L, K::force, K::comp, kNtStores>), c->pairs_grid,
+                                       c->block, 0, c->stream, A, step_args<double>(c), c->pairs_shift);
+                else
+                    hipLaunchKernelGGL((k_step_aa_even_pairs<L, K::force, K::comp, kNtStores>), c->pairs_grid,
+                                       c->block, 0, c->stream, A, step_args<double>(c), c->pairs_shift);
+                return;
+            }
+        }
         if (odd)
             hipLaunchKernelGGL((k_step_aa_odd<L, S, K::walls, K::force, K::comp, kNtStores>), c->grid,
                                c->block, 0, c->stream, A, step_args<typename Store<S>::C>(c));

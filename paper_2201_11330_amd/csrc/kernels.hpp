@@ -529,6 +529,117 @@ __global__ LBM_STEP_BOUNDS void k_step_ab_pairs(const double* __restrict__ src,
     });
 }
 
+// AA steps of a periodic FP64 box with two nodes per work-item (see
+// k_step_ab_pairs for the layout of work-items and the wave shifts).  The
+// even step reads and writes the work-item's own aligned node pairs only.
+// The odd step reads the x-shifted source pairs like k_step_ab_pairs and
+// writes f*_a to the slots it read for abar, which are x-shifted the other
+// way: the aligned destination pair (x0, x0 + 1) takes one value from this
+// work-item and one from its neighbour lane.  A work-item at a wavefront
+// edge or a row end writes its outer value as a single element and the
+// work-item across the edge leaves that element alone, so every address is
+// read and written by one work-item, as the in-place update needs.
+template <int L, bool FORCE, bool COMP, bool NT>
+__global__ LBM_STEP_BOUNDS void k_step_aa_even_pairs(double* __restrict__ A, StepArgs<double> p,
+                                                     int bxl_shift)
+{
+    constexpr int Q = Lattice<L>::Q;
+    const Dims& g = p.g;
+    const int x0 = ((blockIdx.x << bxl_shift) + int(threadIdx.x & ((1u << bxl_shift) - 1u))) * 2;
+    const int y = blockIdx.y * (256 >> bxl_shift) + int(threadIdx.x >> bxl_shift);
+    const int z = blockIdx.z;
+    if (x0 >= g.nx || y >= g.ny) return;
+    const int TS = g.S;
+    const unsigned own = unsigned(x0) + unsigned(g.nx) * (unsigned(y) + unsigned(g.ny) * unsigned(z));
+    double f0[Q], f1[Q];
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        const Pair v = get_pair<NT>(A + slot<Q>(a, own, TS));
+        f0[a] = v.lo;
+        f1[a] = v.hi;
+    });
+    collide<L, double, FORCE, COMP, false>(f0, p.c);
+    collide<L, double, FORCE, COMP, false>(f1, p.c);
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        put_pair(A + slot<Q>(Lattice<L>::opp(a), own, TS), Pair{f0[a], f1[a]});
+    });
+}
+
+template <int L, bool FORCE, bool COMP, bool NT>
+__global__ LBM_STEP_BOUNDS void k_step_aa_odd_pairs(double* __restrict__ A, StepArgs<double> p,
+                                                    int bxl_shift)
+{
+    constexpr int Q = Lattice<L>::Q;
+    const Dims& g = p.g;
+    const int lane = threadIdx.x & 63;
+    const int x0 = ((blockIdx.x << bxl_shift) + int(threadIdx.x & ((1u << bxl_shift) - 1u))) * 2;
+    const int y = blockIdx.y * (256 >> bxl_shift) + int(threadIdx.x >> bxl_shift);
+    const int z = blockIdx.z;
+    // Idle work-items take part in the wave shifts, read row 0 and write
+    // nothing.
+    const bool active = x0 < g.nx && y < g.ny;
+    const int xa = active ? x0 : 0, ya = active ? y : 0;
+    const bool left_edge = lane == 0 || xa == 0;        // x0 - 1 is across an edge
+    const bool right_edge = lane == 63 || xa + 2 >= g.nx;  // x0 + 2 is across an edge
+    const int xl = xa == 0 ? g.nx - 1 : xa - 1;            // x0 - 1, wrapped
+    const int xr = xa + 2 >= g.nx ? 0 : xa + 2;            // x0 + 2, wrapped
+    const int TS = g.S;
+    unsigned row[Q];  // the row of x - e_a, where f_a(x) is read and f*_abar(x) written
+    double f0[Q], f1[Q];
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr int ex = kLattice<L>.e[a][0], ey = kLattice<L>.e[a][1], ez = kLattice<L>.e[a][2];
+        int ys = ya - ey;
+        ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+        int zs = z - ez;
+        if constexpr (kDim<L> == 3) zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
+        else zs = z;
+        row[a] = unsigned(g.nx) * (unsigned(ys) + unsigned(g.ny) * unsigned(zs));
+        constexpr int abar = Lattice<L>::opp(a);
+        const Pair v = get_pair<NT && ex == 0>(A + slot<Q>(abar, row[a] + unsigned(xa), TS));
+        if constexpr (ex == 0) {
+            f0[a] = v.lo;
+            f1[a] = v.hi;
+        } else if constexpr (ex == 1) {  // sources x0 - 1, x0
+            double first = wave_shift<0x138>(v.hi);
+            if (left_edge) first = A[slot<Q>(abar, row[a] + unsigned(xl), TS)];
+            f0[a] = first;
+            f1[a] = v.lo;
+        } else {  // sources x0 + 1, x0 + 2
+            double last = wave_shift<0x130>(v.lo);
+            if (right_edge) last = A[slot<Q>(abar, row[a] + unsigned(xr), TS)];
+            f0[a] = v.hi;
+            f1[a] = last;
+        }
+    });
+    collide<L, double, FORCE, COMP, false>(f0, p.c);
+    collide<L, double, FORCE, COMP, false>(f1, p.c);
+    // f*_a(x) goes to slot a of x + e_a, in the row read for abar.
+    static_for<Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr int ex = kLattice<L>.e[a][0];
+        constexpr int abar = Lattice<L>::opp(a);
+        if constexpr (ex == 0) {
+            if (active) put_pair(A + slot<Q>(a, row[abar] + unsigned(x0), TS), Pair{f0[a], f1[a]});
+        } else if constexpr (ex == 1) {  // destinations x0 + 1, x0 + 2
+            const double from_left = wave_shift<0x138>(f1[a]);  // f*_a(x0 - 1) -> x0
+            if (active) {
+                if (left_edge) put<true>(A + slot<Q>(a, row[abar] + unsigned(x0 + 1), TS), f0[a]);
+                else put_pair(A + slot<Q>(a, row[abar] + unsigned(x0), TS), Pair{from_left, f0[a]});
+                if (right_edge) put<true>(A + slot<Q>(a, row[abar] + unsigned(xr), TS), f1[a]);
+            }
+        } else {  // destinations x0 - 1, x0
+            const double from_right = wave_shift<0x130>(f0[a]);  // f*_a(x0 + 2) -> x0 + 1
+            if (active) {
+                if (right_edge) put<true>(A + slot<Q>(a, row[abar] + unsigned(x0), TS), f1[a]);
+                else put_pair(A + slot<Q>(a, row[abar] + unsigned(x0), TS), Pair{f1[a], from_right});
+                if (left_edge) put<true>(A + slot<Q>(a, row[abar] + unsigned(xl), TS), f0[a]);
+            }
+        }
+    });
+}
+
 // AA even step: own slots in, opposite own slots out.
 template <int L, class S, bool WALLS, bool FORCE, bool COMP, bool NT>
 __global__ LBM_STEP_BOUNDS void k_step_aa_even(S* __restrict__ A,

@@ -128,13 +128,14 @@ def test_aa_equals_ab_bitwise(bc, force):
 ], ids=lambda v: str(v))
 @pytest.mark.parametrize("force,comp", [((0, 0, 0), False), ((1e-5, -2e-5, 0), False),
                                         ((1e-5, 0, 0), True)], ids=["plain", "force", "comp"])
-def test_two_node_kernel_equals_one_node_kernel_bitwise(lattice, dims, force, comp):
-    """Periodic FP64 two-lattice steps of an even-nx box of at least 2^20
-    nodes run two nodes per work-item (16-byte loads, x-shift across lanes;
-    rows inside a wavefront, rows over several workgroups, idle
-    work-items); the AA pattern runs the one-node kernels.  The collision is
-    the same code, so the states agree bit for bit, and both match the
-    oracle."""
+def test_two_node_kernels_ab_equals_aa_bitwise_and_oracle(lattice, dims, force, comp):
+    """Periodic FP64 steps of an even-nx box of at least 2^20 nodes run two
+    nodes per work-item (16-byte accesses, x-shift across lanes; rows inside
+    a wavefront, rows over several workgroups, idle work-items), in the
+    two-lattice pattern and in the in-place AA pattern, whose odd step also
+    writes across lanes.  The two patterns apply the same collision to the
+    same populations, so the states agree bit for bit after every step
+    count (both AA parities), and both match the oracle."""
     assert dims[0] % 2 == 0 and dims[0] * dims[1] * dims[2] >= 1 << 20
     rho, u, noise = inputs(lattice, dims, "channel", seed=12, noise_amp=1e-5, bc=(0, 0, 0), U0=0.03)
     ab = lbm.LBM(lattice, *dims, 0.7, force=force, compressible=comp)

@@ -426,6 +426,14 @@ def main():
                                            "of Eq. (feq)",
                                "mlups": round(mc, 1), "vs_incompressible": round(mc / mlups, 3),
                                "achieved_gbs": round(ac, 1), "frac": round(ac / HBM_PEAK_GBS, 4)}
+        other = "aa" if args.pattern == "ab" else "ab"
+        ro = run_gpu(n, "f64", other, args.steps, args.warmup)
+        mo = nodes * args.steps / (ro["total_ms"] * 1e-3) / 1e6
+        ao = blu * nodes / (ro["launch_ms_mean"] * 1e-3) / 1e9
+        out[f"{other}_pattern"] = {"workload": f"as the main line, {other.upper()} pattern",
+                                   "kernel": step_kernel_name(n, "f64", other),
+                                   "mlups": round(mo, 1), "achieved_gbs": round(ao, 1),
+                                   "frac": round(ao / HBM_PEAK_GBS, 4)}
         out["adjoint"] = run_adjoint()
         out["channel"] = run_channel()
         out["channel_nodal"] = run_channel(nodal=True)

@@ -35,7 +35,7 @@ struct Impl {
     template <class K>
     static void step_ab(lbm_ctx* c, const S* src, S* dst)
     {
-        if constexpr (std::is_same_v<S, double> && !K::walls) {
+        if constexpr (std::is_same_v<S, double> && !K::walls && L != 2) {  // not D3Q27
             if (c->pairs) {
                 hipLaunchKernelGGL((k_step_ab_pairs<L, K::force, K::comp, kNtStores>), c->pairs_grid, c->block,
                                    0, c->stream, src, dst, step_args<double>(c), c->pairs_shift);
@@ -48,7 +48,7 @@ struct Impl {
     template <class K>
     static void step_aa(lbm_ctx* c, S* A, bool odd)
     {
-        if constexpr (std::is_same_v<S, double> && !K::walls) {
+        if constexpr (std::is_same_v<S, double> && !K::walls && L != 2) {  // not D3Q27
             if (c->pairs) {
                 if (odd)
                     hipLaunchKernelGGL((k_step_aa_odd_pairs<L, K::force, K::comp, kNtStores>), c->pairs_grid,

@@ -62,9 +62,12 @@ void plan_launch(lbm_ctx* c)
     c->grid = dim3((c->nx + bx - 1) / bx, (c->ny + by - 1) / by, c->nz);
 
     // Two nodes per work-item: nx/2 work-items per row.  Only on boxes of at
-    // least 2^20 nodes: a small box is bound by launch latency and runs
-    // faster with twice the workgroups of the one-node kernel.
-    c->pairs = c->storage == LBM_F64 && c->nx % 2 == 0 && c->N >= (1u << 20);
+    // least 2^20 nodes (a small box is bound by launch latency and runs
+    // faster with twice the workgroups of the one-node kernel) and not for
+    // D3Q27, whose 54 populations per work-item cost more occupancy than the
+    // wider accesses gain (measured 2-4 % slower).
+    c->pairs = c->storage == LBM_F64 && c->lattice != LBM_D3Q27 && c->nx % 2 == 0 &&
+               c->N >= (1u << 20);
     if (c->pairs) {
         const int half = c->nx / 2;
         int lanes = 1, s2 = 0;

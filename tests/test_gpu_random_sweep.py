@@ -1,0 +1,76 @@
+"""Seeded random sweep of configurations against the oracle (FP64, 1e-12):
+lattice, box shape (ragged, thin, single-node axes), boundary kind per axis
+(periodic, solid ends, walls outside, nodal walls), body force, equilibrium
+model, propagation pattern, random solid masks and step counts.  Each case
+prints its configuration before it runs."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_11330_amd import lbm
+from paper_2201_11330_amd import workloads as W
+from parity_utils import rel_err, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+N_CASES = 48
+
+
+def _case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    lattice = int(rng.choice([W.D2Q9, W.D3Q19, W.D3Q27]))
+    D = 2 if lattice == W.D2Q9 else 3
+    bc = [W.PERIODIC] * 3
+    for d in range(D):
+        bc[d] = int(rng.choice([W.PERIODIC, W.SOLID_ENDS, W.WALLS_OUTSIDE, W.WALLS_NODAL],
+                               p=[0.4, 0.2, 0.2, 0.2]))
+    nodal = [d for d in range(3) if bc[d] == W.WALLS_NODAL]
+    for d in nodal[1:]:  # one nodal axis at most
+        bc[d] = W.SOLID_ENDS
+    dims = []
+    for d in range(3):
+        if d == 2 and D == 2:
+            dims.append(1)
+            continue
+        lo = 3 if bc[d] != W.PERIODIC else 1
+        dims.append(int(rng.integers(lo, 41 if d == 0 else 24)))
+    force = np.zeros(3)
+    if rng.random() < 0.7:
+        force[:D] = 2e-5 * rng.standard_normal(D)
+    comp = bool(rng.random() < 0.4)
+    aa = bool(rng.random() < 0.5)
+    steps = int(rng.integers(1, 13))
+    tau = float(rng.uniform(0.52, 1.5))
+    solid = None
+    if rng.random() < 0.35:
+        nz, ny, nx = dims[2], dims[1], dims[0]
+        solid = (rng.random((nz, ny, nx)) < 0.12).astype(np.uint8)
+    return lattice, tuple(dims), tuple(bc), tuple(force), comp, aa, steps, tau, solid
+
+
+def _inputs(lattice, dims, seed):
+    nx, ny, nz = dims
+    rng = np.random.default_rng(2000 + seed)
+    rho = 1.0 + 0.05 * rng.uniform(-1, 1, (nz, ny, nx))
+    u = 0.04 * rng.standard_normal((3, nz, ny, nx))
+    if lattice == W.D2Q9:
+        u[2] = 0.0
+    noise = 1e-4 * rng.standard_normal((W.Q_OF[lattice], nz, ny, nx))
+    return rho, u, noise
+
+
+@pytest.mark.parametrize("seed", range(N_CASES))
+def test_random_configuration_matches_oracle(seed):
+    lattice, dims, bc, force, comp, aa, steps, tau, solid = _case(seed)
+    print(f"seed {seed}: Q{W.Q_OF[lattice]} dims={dims} bc={bc} F={force} comp={comp} aa={aa} "
+          f"steps={steps} tau={tau:.3f} mask={'yes' if solid is not None else 'no'}", flush=True)
+    rho, u, noise = _inputs(lattice, dims, seed)
+    f_or, r_or, u_or, red_or = run_oracle(lattice, dims, tau, force, bc, rho, u, noise, steps,
+                                          solid=solid, compressible=comp)
+    f, r, v, red = run_gpu(lattice, dims, tau, force, bc, rho, u, noise, steps, aa=aa,
+                           solid=solid, compressible=comp)
+    ef, er, eu = rel_err(f, f_or), rel_err(r, r_or), rel_err(v, u_or)
+    print(f"  f {ef:.2e} rho {er:.2e} u {eu:.2e}", flush=True)
+    assert ef <= TOL and er <= TOL and eu <= TOL
+    assert abs(red["mass"] - red_or["mass"]) <= TOL * max(abs(red_or["mass"]), 1.0)

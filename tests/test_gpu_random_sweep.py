@@ -70,7 +70,11 @@ def test_random_configuration_matches_oracle(seed):
                                           solid=solid, compressible=comp)
     f, r, v, red = run_gpu(lattice, dims, tau, force, bc, rho, u, noise, steps, aa=aa,
                            solid=solid, compressible=comp)
-    ef, er, eu = rel_err(f, f_or), rel_err(r, r_or), rel_err(v, u_or)
+    ef, er = rel_err(f, f_or), rel_err(r, r_or)
+    # u relative to the flow's velocity scale: in a box a few nodes wide the
+    # final field can decay by orders of magnitude, and its own maximum is
+    # then no longer the scale that rounding errors follow.
+    eu = np.abs(v - u_or).max() / max(np.abs(u_or).max(), np.abs(u).max())
     print(f"  f {ef:.2e} rho {er:.2e} u {eu:.2e}", flush=True)
     assert ef <= TOL and er <= TOL and eu <= TOL
     assert abs(red["mass"] - red_or["mass"]) <= TOL * max(abs(red_or["mass"]), 1.0)

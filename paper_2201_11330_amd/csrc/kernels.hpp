@@ -3,10 +3,11 @@
 // Layout: nodes are numbered x + nx*(y + ny*z) (x fastest).  A population
 // buffer is an array of tiles of T = 2^S consecutive nodes; a tile holds Q
 // runs of T elements, one per direction (structure of arrays inside the
-// tile, see slot()).  One work-item owns one node; 256-item workgroups
-// cover a (BX x BY) tile of an x-y plane with BX a power of two (the full
-// row when nx <= 256), so the 64 lanes of a wavefront touch 64 consecutive
-// nodes of a row and every access is a coalesced 64-element run.  The 19
+// tile, see slot()).  One work-item owns one node (two in the *_pairs
+// kernels); 256-item workgroups cover a (BX x BY) tile of an x-y plane with
+// BX a power of two (the full row when nx <= 256), so the 64 lanes of a
+// wavefront touch 64 consecutive nodes of a row and every access is a
+// coalesced 64-element run.  The 19
 // loads and 19 stores of a wavefront land in a few contiguous regions
 // instead of 19 separate planes (measured 4-10 % faster than plain
 // structure of arrays on MI355X).

@@ -309,9 +309,10 @@ __device__ __forceinline__ S get(const S* p)
     }
 }
 
-// Workgroups of the step kernels: 256 work-items; the compiler may use up
-// to 128 VGPRs so that all Q loads of a work-item are in flight before the
-// collision (measured faster than forcing 8 waves per SIMD).
+// Workgroups of the step kernels: 256 work-items; the occupancy bound lets
+// the compiler take the VGPRs it needs to keep all Q loads of a work-item in
+// flight before the collision (measured faster than forcing 8 waves per
+// SIMD).
 #define LBM_STEP_BOUNDS __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 8)))
 
 // ---------------------------------------------------------------------------

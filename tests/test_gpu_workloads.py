@@ -50,6 +50,36 @@ def test_poiseuille_steady_3d(walls, aa):
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("walls", [W.SOLID_ENDS, W.WALLS_NODAL], ids=["halfway", "nodal"])
+def test_channel_full_height_steady_state(walls):
+    """The channel workload's height (128 nodes across y, g_x = 1e-6,
+    tau = 0.9) run to steady state on a narrow periodic box: 250,000 steps,
+    after which the slowest mode has decayed to exp(-nu (pi/H)^2 t) ~ 1e-9.
+    The profile equals the closed form of the wall type (halfway: walls at
+    0.5 and 126.5; nodal: walls on the nodes 0 and 127)."""
+    nx, ny, nz, tau, g = 4, 128, 4, 0.9, 1e-6
+    nu = (tau - 0.5) / 3
+    sim = lbm.LBM(lbm.D3Q19, nx, ny, nz, tau, force=(g, 0, 0), bc=(0, walls, 0), graph=True)
+    sim.init_equilibrium(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    y = np.arange(ny, dtype=float)
+    if walls == W.SOLID_ENDS:
+        H, fl = ny - 2, slice(1, ny - 1)
+        want = g / (2 * nu) * (y - 0.5) * (ny - 1.5 - y) + g * (16 * (tau - 0.5) ** 2 - 3) / (24 * nu)
+    else:
+        H, fl = ny - 1, slice(0, ny)
+        want = g / (2 * nu) * y * (H - y) + (2 * tau + 0.5) * g
+    steps = 250_000
+    for k in range(5):
+        sim.step(steps // 5)
+        print(f"step {(k + 1) * steps // 5}", flush=True)
+    _, u = sim.moments()
+    prof = u[0].cpu().numpy()[:, fl, :]
+    err = np.abs(prof - want[None, fl, None]).max() / want[fl].max()
+    print(f"full-height channel ({'halfway' if walls == W.SOLID_ENDS else 'nodal'}): "
+          f"{err:.2e} (transient {math.exp(-nu * (math.pi / H) ** 2 * steps):.1e})")
+    assert err < 1e-8
+
+
 def test_channel_workload_20000_steps():
     """Workload D3Q19 512 x 128 x 128 channel, g_x = 1e-6, tau = 0.9, 20000
     steps: the x-z averaged u_x(y) equals a 1-column oracle run (same walls,

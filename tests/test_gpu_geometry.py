@@ -205,3 +205,44 @@ def test_paper_sphere_box_sampled():
                                   centers, solid=solid)
     print(f"paper sphere box sampled: f {ef:.2e} u {eu:.2e}")
     assert ef <= TOL and eu <= TOL
+
+
+@pytest.mark.parametrize("aa", [False, True], ids=["AB", "AA"])
+def test_degenerate_masks(aa):
+    """An all-solid box (no fluid node: the state, moments, monitor and wall
+    force are all zero) and a single fluid node whose every link is a wall
+    (each population comes back reversed; mass is kept, and the node's
+    populations match the oracle's) in the AB and AA patterns."""
+    dims = (6, 5, 4)
+    nx, ny, nz = dims
+    rho = 1.0 + 0.01 * np.random.default_rng(3).standard_normal((nz, ny, nx))
+    u = 0.02 * np.random.default_rng(4).standard_normal((3, nz, ny, nx))
+    full = np.ones((nz, ny, nx), dtype=np.uint8)
+    sim = lbm.LBM(W.D3Q19, *dims, 0.8, force=(1e-5, 0, 0), aa=aa)
+    sim.set_solid(full)
+    sim.init_equilibrium(rho, u)
+    sim.step(3)
+    assert not sim.get_populations().abs().max().item()
+    r, v = sim.moments()
+    assert not r.abs().max().item() and not v.abs().max().item()
+    red = sim.reduce()
+    assert red["mass"] == 0.0 and red["ke"] == 0.0 and not red["unstable"]
+    assert sim.wall_force() == [0.0, 0.0, 0.0]
+    sim.close()
+
+    one = full.copy()
+    one[2, 2, 3] = 0
+    s = oracle.Sim(W.D3Q27, *dims, tau=0.8, force=(1e-5, 0, 0))
+    s.set_solid(one)
+    s.init_equilibrium(rho, u)
+    m0 = s.reduce()["mass"]
+    s.step(5)
+    sim = lbm.LBM(W.D3Q27, *dims, 0.8, force=(1e-5, 0, 0), aa=aa)
+    sim.set_solid(one)
+    sim.init_equilibrium(rho, u)
+    sim.step(5)
+    f = sim.get_populations().cpu().numpy()
+    assert rel_err(f, s.get_populations()) <= TOL
+    assert abs(sim.reduce()["mass"] - m0) <= 1e-15
+    assert np.abs(np.asarray(sim.wall_force()) - np.asarray(s.wall_force())).max() <= 1e-15
+    sim.close()

@@ -6,6 +6,8 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "liblbm.so")
+EXAMPLE_SRC = os.path.join(PKG, "examples", "lbm_channel.c")
+EXAMPLE_BIN = os.path.join(PKG, "examples", "lbm_channel")
 SOURCES = [os.path.join(PKG, "csrc", name) for name in
            ("lbm.hip", "lattice_d2q9.hip", "lattice_d3q19.hip", "lattice_d3q27.hip")]
 BUILD_DIR = os.path.join(PKG, "_build")
@@ -59,7 +61,26 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed ({res.returncode}):\n{_filtered(res.stdout + res.stderr)}")
     os.replace(LIB + ".tmp", LIB)
+    build_example(verbose)
     return LIB
+
+
+def build_example(verbose: bool = False) -> str:
+    """Compiles the C99 driver examples/lbm_channel.c against include/lbm.h
+    and liblbm.so (plain C compiler; the HIP runtime API header selects the
+    AMD platform by the macro hipcc would define)."""
+    cc = os.environ.get("CC", "gcc")
+    cmd = [cc, "-std=c99", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+           "-o", EXAMPLE_BIN + ".tmp", EXAMPLE_SRC, "-L", PKG, "-llbm",
+           "-L", "/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,$ORIGIN/.."]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"example build failed:\n{res.stdout}{res.stderr}")
+    os.replace(EXAMPLE_BIN + ".tmp", EXAMPLE_BIN)
+    return EXAMPLE_BIN
 
 
 if __name__ == "__main__":

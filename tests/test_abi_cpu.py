@@ -135,3 +135,14 @@ def test_status_strings():
     for st in (lbm.OK, lbm.EINVAL, lbm.ENOTBOUND, lbm.EHIP, lbm.EUNSTABLE, lbm.ESTATE):
         assert L.lbm_status_string(st)
     assert L.lbm_status_string(123) == b"unknown status"
+
+
+def test_c_example_is_built_and_checks_its_arguments():
+    """The C99 driver links against liblbm.so and, given no arguments, prints
+    its usage and exits with status 2 before any HIP call."""
+    import subprocess
+    from paper_2201_11330_amd import build as pkg_build
+    exe = pkg_build.EXAMPLE_BIN
+    assert os.path.exists(exe)
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert res.returncode == 2 and "usage" in res.stderr

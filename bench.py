@@ -334,15 +334,23 @@ def cpu_baseline(n, target_s):
     t0 = time.perf_counter()
     s.step(k)
     dt = time.perf_counter() - t0
+    cores = oracle.num_threads()
+    # one more step on a single thread, for the per-core rate
+    oracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    s.step(1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_num_threads(cores)
     s.close()
     mlups = n ** 3 * k / dt / 1e6
     return {
         "value": round(mlups, 3),
         "unit": "MLUPS",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"D3Q19 {n}^3 FP64 Taylor-Green, {k} whole-domain steps after 1 untimed "
-                  f"({dt:.1f} s), AoS paper-order oracle, OpenMP",
+                  f"({dt:.1f} s), AoS paper-order oracle, OpenMP; then 1 step on 1 thread",
+        "single_thread_mlups": round(n ** 3 / dt1 / 1e6, 3),
         "cpu_model": host_cpu_model(),
     }
 

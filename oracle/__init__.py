@@ -59,8 +59,14 @@ def _load():
     lib.orc_wall_force.argtypes = [vp, _dp]
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
     return lib
+
+
+def set_num_threads(n):
+    """Thread count of the oracle's parallel loops."""
+    _check(_load().orc_set_num_threads(int(n)), "set_num_threads")
 
 
 def num_threads():

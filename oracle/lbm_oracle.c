@@ -537,6 +537,14 @@ int orc_set_compressible(orc_sim* s, int comp)
 /* Threads the oracle's parallel loops use (reported with its timings). */
 int orc_num_threads(void) { return omp_get_max_threads(); }
 
+/* Sets the thread count of the parallel loops (n >= 1). */
+int orc_set_num_threads(int n)
+{
+    if (n < 1) return ORC_EINVAL;
+    omp_set_num_threads(n);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Node-level entry points for the pins.                                     */
 

@@ -36,6 +36,7 @@ int orc_wall_force(const orc_sim* s, double F[3]);
 int orc_reduce(const orc_sim* s, double* mass, double* ke, double* umax, long* nonfinite);
 
 int orc_num_threads(void);
+int orc_set_num_threads(int n);
 
 int orc_lattice_tables(int lattice, int* Q, int* D, int* e, double* t);
 int orc_set_compressible(orc_sim* s, int comp);

@@ -163,6 +163,8 @@ class LBM:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         check(L.lbm_bind(h, _ptr(self.buffers[0]), _ptr(self.buffers[1]) if not self.aa else None,
                          ctypes.c_void_p(self.stream.cuda_stream)), "lbm_bind")
+        for b in self.buffers:  # used on the context's stream until freed
+            b.record_stream(self.stream)
 
     # -- life cycle ---------------------------------------------------------
     def close(self):
@@ -182,27 +184,55 @@ class LBM:
     def __exit__(self, *exc):
         self.close()
 
+    # -- streams ------------------------------------------------------------
+    # Tensors are made (and host data copied in) on torch's current stream,
+    # while the library runs on the context's stream.  Before a call the
+    # context's stream waits for the current one, and every device tensor the
+    # call uses is recorded on the context's stream (the caching allocator then
+    # keeps its memory until that stream has passed it); after the call the
+    # current stream waits for the context's stream, so results are ready
+    # there.  With the default stream choice both are the same stream and
+    # nothing waits.
+    def _enter(self, *tensors):
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.stream)
+
+    def _leave(self):
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
     # -- state --------------------------------------------------------------
     def init_equilibrium(self, rho, u, noise=None):
         rho = _dev_f64(rho, self.shape, self.device)
         u = _dev_f64(u, (3,) + self.shape, self.device)
         noise = _dev_f64(noise, (self.Q,) + self.shape, self.device)
-        self._keep = (rho, u, noise)  # alive until the stream has consumed them
+        self._enter(rho, u, noise)
         check(lib().lbm_init_equilibrium(self._h, _ptr(rho), _ptr(u), _ptr(noise)),
               "lbm_init_equilibrium")
+        self._leave()
 
     def set_populations(self, f):
         f = _dev_f64(f, (self.Q,) + self.shape, self.device)
-        self._keep = (f,)
+        self._enter(f)
         check(lib().lbm_set_populations(self._h, _ptr(f)), "lbm_set_populations")
+        self._leave()
 
     def get_populations(self):
         f = torch.empty((self.Q,) + self.shape, dtype=torch.float64, device=self.device)
+        self._enter(f)
         check(lib().lbm_get_populations(self._h, _ptr(f)), "lbm_get_populations")
+        self._leave()
         return f
 
     def step(self, n=1):
+        self._enter()
         check(lib().lbm_step(self._h, int(n)), "lbm_step")
+        self._leave()
 
     @property
     def steps_taken(self):
@@ -215,8 +245,10 @@ class LBM:
             rho = torch.empty(self.shape, dtype=dtype, device=self.device)
         if u is None:
             u = torch.empty((3,) + self.shape, dtype=dtype, device=self.device)
+        self._enter(rho, u)
         check(lib().lbm_moments(self._h, _ptr(rho), _ptr(u), 1 if dtype == torch.float32 else 0),
               "lbm_moments")
+        self._leave()
         return rho, u
 
     # -- geometry -------------------------------------------------------------
@@ -225,12 +257,14 @@ class LBM:
         if not isinstance(solid, torch.Tensor):
             solid = torch.from_numpy(np.ascontiguousarray(np.asarray(solid), dtype=np.uint8))
         m = solid.to(device=self.device, dtype=torch.uint8).reshape(self.shape).contiguous()
-        self._keep = (m,)
+        self._enter(m)
         check(lib().lbm_set_solid(self._h, _ptr(m)), "lbm_set_solid")
+        self._leave()
 
     def wall_force(self):
         """Momentum-exchange force on the walls during the last propagation."""
         F = (ctypes.c_double * 3)()
+        self._enter()
         check(lib().lbm_wall_force(self._h, F), "lbm_wall_force")
         return [F[0], F[1], F[2]]
 
@@ -245,7 +279,9 @@ class LBM:
         if ckpt is None:
             ckpt = torch.empty(max(n // k, 1) * self.buffer_bytes, dtype=torch.uint8,
                                device=self.device)
+        self._enter(ckpt)
         check(lib().lbm_forward_record(self._h, int(n), int(k), _ptr(ckpt)), "lbm_forward_record")
+        self._leave()
         return ckpt
 
     def adjoint(self, n, k, ckpt, u0, dJ_du, work=None, rho0=None):
@@ -261,14 +297,17 @@ class LBM:
         u0bar = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
         taubar = ctypes.c_double()
         Fbar = (ctypes.c_double * 3)()
+        self._enter(ckpt, work, rho0, u0, dJ_du, u0bar)
         check(lib().lbm_adjoint(self._h, int(n), int(k), _ptr(ckpt), _ptr(work), _ptr(rho0),
                                 _ptr(u0), _ptr(dJ_du), _ptr(u0bar), ctypes.byref(taubar), Fbar),
               "lbm_adjoint")
+        self._leave()
         return u0bar, taubar.value, [Fbar[0], Fbar[1], Fbar[2]]
 
     def reduce(self):
         """Monitor: {'mass', 'ke', 'umax'} in FP64 (synchronises the stream)."""
         m, k, um = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._enter()
         st = lib().lbm_reduce(self._h, ctypes.byref(m), ctypes.byref(k), ctypes.byref(um))
         out = {"mass": m.value, "ke": k.value, "umax": um.value,
                "unstable": st == EUNSTABLE}

@@ -43,7 +43,10 @@
  *     context.  The library owns the context and a small device scratch for
  *     reductions, allocated in lbm_bind and freed in lbm_destroy.
  *   - Every call returns LBM_OK (0) or a negative lbm_status and never
- *     throws.  Arguments are checked on the host before any launch.  A HIP
+ *     throws.  Arguments are checked on the host before any launch; a
+ *     device pointer must be device (or managed) memory of the current
+ *     device whose allocation extends at least as far past the pointer as
+ *     the call reads or writes (LBM_EINVAL otherwise).  A HIP
  *     failure returns LBM_EHIP; lbm_last_error() then holds the HIP error
  *     text.  Kernel faults are asynchronous and surface at the next call
  *     that synchronises.  A context is not thread-safe; separate contexts

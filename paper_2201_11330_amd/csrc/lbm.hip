@@ -97,7 +97,10 @@ lbm_status need_state(const lbm_ctx* c)
     return LBM_OK;
 }
 
-lbm_status check_device_ptr(const void* p, const char* name, bool allow_null)
+// Checks that p is device (or managed) memory on the current device and,
+// when bytes > 0, that the allocation holding p extends at least bytes past
+// it, so that no kernel of the call can touch memory outside it.
+lbm_status check_device_ptr(const void* p, const char* name, bool allow_null, size_t bytes = 0)
 {
     if (!p) return allow_null ? LBM_OK : fail(LBM_EINVAL, "%s is NULL", name);
     hipPointerAttribute_t attr;
@@ -111,6 +114,19 @@ lbm_status check_device_ptr(const void* p, const char* name, bool allow_null)
     int dev = -1;
     LBM_HIP(hipGetDevice(&dev));
     if (attr.device != dev) return fail(LBM_EINVAL, "%s is on device %d, current is %d", name, attr.device, dev);
+    if (bytes > 0) {
+        hipDeviceptr_t base = nullptr;
+        size_t size = 0;
+        e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_EINVAL, "%s: the allocation holding it is unknown", name);
+        }
+        const size_t offset = static_cast<size_t>(static_cast<const char*>(p) - static_cast<const char*>(base));
+        if (offset > size || size - offset < bytes)
+            return fail(LBM_EINVAL, "%s holds %zu bytes from the pointer, the call needs %zu", name,
+                        offset > size ? size_t(0) : size - offset, bytes);
+    }
     return LBM_OK;
 }
 
@@ -202,12 +218,13 @@ lbm_status lbm_bind(lbm_ctx* c, void* buf_a, void* buf_b, void* hip_stream)
 {
     if (!c) return fail(LBM_EINVAL, "null context");
     if (c->bound) return fail(LBM_ESTATE, "context already bound");
-    lbm_status st = check_device_ptr(buf_a, "buf_a", false);
+    const size_t bb = lbm_buffer_bytes(c);
+    lbm_status st = check_device_ptr(buf_a, "buf_a", false, bb);
     if (st) return st;
     if (c->aa) {
         if (buf_b) return fail(LBM_EINVAL, "buf_b must be NULL with LBM_FLAG_AA");
     } else {
-        st = check_device_ptr(buf_b, "buf_b", false);
+        st = check_device_ptr(buf_b, "buf_b", false, bb);
         if (st) return st;
         if (buf_a == buf_b) return fail(LBM_EINVAL, "buf_a and buf_b are the same buffer");
     }
@@ -233,9 +250,10 @@ lbm_status lbm_init_equilibrium(lbm_ctx* c, const double* rho, const double* u, 
 {
     lbm_status st = need_bound(c);
     if (st) return st;
-    if ((st = check_device_ptr(rho, "rho", false))) return st;
-    if ((st = check_device_ptr(u, "u", false))) return st;
-    if ((st = check_device_ptr(noise, "noise", true))) return st;
+    const size_t field = sizeof(double) * size_t(c->N);
+    if ((st = check_device_ptr(rho, "rho", false, field))) return st;
+    if ((st = check_device_ptr(u, "u", false, 3 * field))) return st;
+    if ((st = check_device_ptr(noise, "noise", true, size_t(c->Q) * field))) return st;
     c->steps = 0;
     c->cur = 0;
     c->state_valid = false;
@@ -248,7 +266,7 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* f)
 {
     lbm_status st = need_bound(c);
     if (st) return st;
-    if ((st = check_device_ptr(f, "f", false))) return st;
+    if ((st = check_device_ptr(f, "f", false, sizeof(double) * size_t(c->Q) * c->N))) return st;
     c->steps = 0;
     c->cur = 0;
     c->state_valid = false;
@@ -261,7 +279,7 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* f)
 {
     lbm_status st = need_state(c);
     if (st) return st;
-    if ((st = check_device_ptr(f, "f", false))) return st;
+    if ((st = check_device_ptr(f, "f", false, sizeof(double) * size_t(c->Q) * c->N))) return st;
     return c->ops->export_f(c, f);
 }
 
@@ -277,8 +295,9 @@ lbm_status lbm_moments(lbm_ctx* c, void* rho, void* u, int out_is_f32)
 {
     lbm_status st = need_state(c);
     if (st) return st;
-    if ((st = check_device_ptr(rho, "rho", true))) return st;
-    if ((st = check_device_ptr(u, "u", true))) return st;
+    const size_t field = (out_is_f32 ? sizeof(float) : sizeof(double)) * size_t(c->N);
+    if ((st = check_device_ptr(rho, "rho", true, field))) return st;
+    if ((st = check_device_ptr(u, "u", true, 3 * field))) return st;
     if (!rho && !u) return LBM_OK;
     return c->ops->moments(c, rho, u, out_is_f32);
 }
@@ -305,7 +324,7 @@ lbm_status lbm_set_solid(lbm_ctx* c, const unsigned char* solid)
 {
     lbm_status st = need_bound(c);
     if (st) return st;
-    if ((st = check_device_ptr(solid, "solid", false))) return st;
+    if ((st = check_device_ptr(solid, "solid", false, size_t(c->N)))) return st;
     if (c->graph_exec) return fail(LBM_ESTATE, "lbm_set_solid after a graph was captured");
     if (!c->links) LBM_HIP(hipMalloc(&c->links, sizeof(unsigned) * size_t(c->N)));
     c->walls = true;
@@ -333,8 +352,8 @@ lbm_status lbm_forward_record(lbm_ctx* c, int n, int k, void* ckpt)
     if (c->aa) return fail(LBM_EINVAL, "checkpointed runs need the two-lattice pattern (no LBM_FLAG_AA)");
     if (n < 0 || k < 1 || n % k != 0) return fail(LBM_EINVAL, "need n >= 0, k >= 1 and k dividing n (n=%d k=%d)", n, k);
     if (n == 0) return LBM_OK;
-    if ((st = check_device_ptr(ckpt, "ckpt", false))) return st;
     const size_t bytes = lbm_buffer_bytes(c);
+    if ((st = check_device_ptr(ckpt, "ckpt", false, size_t(n / k) * bytes))) return st;
     char* ck = static_cast<char*>(ckpt);
     for (int s = 0; s < n / k; ++s) {
         LBM_HIP(hipMemcpyAsync(ck + size_t(s) * bytes, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice,
@@ -360,12 +379,13 @@ lbm_status lbm_adjoint(lbm_ctx* c, int n, int k, const void* ckpt, void* work, c
     if (n < 0 || k < 1 || n % k != 0) return fail(LBM_EINVAL, "need n >= 0, k >= 1 and k dividing n (n=%d k=%d)", n, k);
     if (std::isinf(c->tau)) return fail(LBM_EINVAL, "the adjoint needs a finite tau");
     if (c->comp && n < 1) return fail(LBM_EINVAL, "the compressible adjoint needs n >= 1");
-    if (c->comp && (st = check_device_ptr(rho0, "rho0", false))) return st;
-    if (n > 0 && (st = check_device_ptr(ckpt, "ckpt", false))) return st;
-    if ((st = check_device_ptr(work, "work", false))) return st;
-    if ((st = check_device_ptr(u0, "u0", false))) return st;
-    if ((st = check_device_ptr(dJ_du, "dJ_du", false))) return st;
-    if ((st = check_device_ptr(dJ_du0, "dJ_du0", false))) return st;
+    const size_t field = sizeof(double) * size_t(c->N);
+    if (c->comp && (st = check_device_ptr(rho0, "rho0", false, field))) return st;
+    if (n > 0 && (st = check_device_ptr(ckpt, "ckpt", false, size_t(n / k) * lbm_buffer_bytes(c)))) return st;
+    if ((st = check_device_ptr(work, "work", false, lbm_adjoint_workspace_bytes(c, k)))) return st;
+    if ((st = check_device_ptr(u0, "u0", false, 3 * field))) return st;
+    if ((st = check_device_ptr(dJ_du, "dJ_du", false, 3 * field))) return st;
+    if ((st = check_device_ptr(dJ_du0, "dJ_du0", false, 3 * field))) return st;
     if (reinterpret_cast<uintptr_t>(work) & 255) return fail(LBM_EINVAL, "work must be 256-byte aligned");
     double out[4];
     if ((st = c->ops->adjoint(c, n, k, ckpt, work, rho0, u0, dJ_du, dJ_du0, c->h_result))) return st;

@@ -376,3 +376,38 @@ def test_graph_replay_of_two_node_kernels(aa):
         g.step(k)
         e.step(k)
         assert torch.equal(g.get_populations(), e.get_populations())
+
+
+def test_buffers_too_small_for_the_call_are_rejected():
+    """Every device buffer is checked against the allocation that holds it
+    (hipMemGetAddressRange) before any launch: buffers too small for what
+    the call reads or writes give LBM_EINVAL, and the context stays usable."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    dims = (64, 64, 32)
+    N = 64 * 64 * 32
+    rho = torch.ones(dims[::-1], dtype=torch.float64, device="cuda")
+    u = torch.zeros((3,) + dims[::-1], dtype=torch.float64, device="cuda")
+    sim = lbm.LBM(lbm.D3Q19, *dims, 0.7)
+    sim.init_equilibrium(rho, u)
+    L = lbm.lib()
+    small = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(small), ctypes.c_size_t(8 * N)) == 0  # one FP64 field
+    try:
+        assert L.lbm_set_populations(sim._h, small) == lbm.EINVAL  # needs Q fields
+        assert b"needs" in L.lbm_last_error()
+        assert L.lbm_get_populations(sim._h, small) == lbm.EINVAL
+        assert L.lbm_init_equilibrium(sim._h, small, small, None) == lbm.EINVAL  # u is [3][N]
+        off = ctypes.c_void_p(small.value + 8)  # one element short of a field
+        assert L.lbm_moments(sim._h, off, None, 0) == lbm.EINVAL
+        assert L.lbm_moments(sim._h, small, None, 0) == lbm.OK  # exactly one field
+        ctx = ctypes.c_void_p()
+        F = (ctypes.c_double * 3)()
+        assert L.lbm_create(ctypes.byref(ctx), lbm.D3Q19, *dims, 0.7, F, None, lbm.F64, 0) == lbm.OK
+        assert L.lbm_bind(ctx, small, small, None) == lbm.EINVAL  # not a population buffer
+        L.lbm_destroy(ctx)
+        sim.step(2)
+        assert sim.reduce()["mass"] > 0
+    finally:
+        torch.cuda.synchronize()
+        hip.hipFree(small)

@@ -35,7 +35,10 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    # 100 untimed steps: after the host-side input generation leaves the GPU
+    # idle, the short FP16 launches take ~100 launches (~20 ms) to reach
+    # their steady duration (FP64: ~5).
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=256, help="cube edge of the workload")
     ap.add_argument("--storage", default="f64", choices=sorted(STORAGE_BYTES))
     ap.add_argument("--pattern", default="ab", choices=["ab", "aa"])

@@ -540,7 +540,11 @@ __global__ LBM_STEP_BOUNDS void k_step_ab_pairs(const double* __restrict__ src,
 // work-item and one from its neighbour lane.  A work-item at a wavefront
 // edge or a row end writes its outer value as a single element and the
 // work-item across the edge leaves that element alone, so every address is
-// read and written by one work-item, as the in-place update needs.
+// read and written by one work-item, as the in-place update needs.  Those
+// single elements go through the cache (not non-temporal): their lines are
+// completed by the neighbouring wavefront's stores and then leave L2 as
+// whole lines (with non-temporal edge stores 2 % more bytes reached HBM and
+// the odd step ran 5 % slower on MI355X).
 template <int L, bool FORCE, bool COMP, bool NT>
 __global__ LBM_STEP_BOUNDS void k_step_aa_even_pairs(double* __restrict__ A, StepArgs<double> p,
                                                      int bxl_shift)
@@ -627,16 +631,16 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_odd_pairs(double* __restrict__ A, Step
         } else if constexpr (ex == 1) {  // destinations x0 + 1, x0 + 2
             const double from_left = wave_shift<0x138>(f1[a]);  // f*_a(x0 - 1) -> x0
             if (active) {
-                if (left_edge) put<true>(A + slot<Q>(a, row[abar] + unsigned(x0 + 1), TS), f0[a]);
+                if (left_edge) put<false>(A + slot<Q>(a, row[abar] + unsigned(x0 + 1), TS), f0[a]);
                 else put_pair(A + slot<Q>(a, row[abar] + unsigned(x0), TS), Pair{from_left, f0[a]});
-                if (right_edge) put<true>(A + slot<Q>(a, row[abar] + unsigned(xr), TS), f1[a]);
+                if (right_edge) put<false>(A + slot<Q>(a, row[abar] + unsigned(xr), TS), f1[a]);
             }
         } else {  // destinations x0 - 1, x0
             const double from_right = wave_shift<0x130>(f0[a]);  // f*_a(x0 + 2) -> x0 + 1
             if (active) {
-                if (right_edge) put<true>(A + slot<Q>(a, row[abar] + unsigned(x0), TS), f1[a]);
+                if (right_edge) put<false>(A + slot<Q>(a, row[abar] + unsigned(x0), TS), f1[a]);
                 else put_pair(A + slot<Q>(a, row[abar] + unsigned(x0), TS), Pair{f1[a], from_right});
-                if (left_edge) put<true>(A + slot<Q>(a, row[abar] + unsigned(xl), TS), f0[a]);
+                if (left_edge) put<false>(A + slot<Q>(a, row[abar] + unsigned(xl), TS), f0[a]);
             }
         }
     });

@@ -3,8 +3,12 @@
 #pragma once
 
 #include "context.hpp"
+#include "fused2d.hpp"
 
 namespace imexlbm {
+
+// A captured run holds whole pairs of fused launches (see eager()).
+static_assert(kGraphSteps % (2 * kFuseSteps) == 0, "graph length must be a multiple of 2 * kFuseSteps");
 
 // Compile-time configuration of the step kernels: walls or masks present,
 // body force, compressible equilibrium (which always takes the force path).
@@ -121,9 +125,35 @@ struct Impl {
         return eager(c, n);
     }
 
+    // kFuseSteps steps of a periodic D2Q9 two-lattice box in one launch.
+    template <class K>
+    static void step_fused2d(lbm_ctx* c, const S* src, S* dst)
+    {
+        const dim3 grid((c->nx + kFuseInner - 1) / kFuseInner, (c->ny + kFuseInner - 1) / kFuseInner, 1);
+        hipLaunchKernelGGL((k_step_ab_fused2d<S, K::force, K::comp, kNtStores>), grid, c->block, 0, c->stream,
+                           src, dst, step_args<typename Store<S>::C>(c));
+    }
+
     static lbm_status eager(lbm_ctx* c, int n)
     {
-        for (int i = 0; i < n; ++i) {
+        int i = 0;
+        if constexpr (L == 0) {
+            // Periodic D2Q9, two lattices: launches of kFuseSteps steps, in
+            // pairs so that the current buffer keeps following the parity of
+            // the step count; the remainder runs one step per launch.
+            if (!c->aa && !c->walls) {
+                for (; n - i >= 2 * kFuseSteps; i += 2 * kFuseSteps) {
+                    for (int h = 0; h < 2; ++h) {
+                        const S* src = static_cast<const S*>(c->buf[c->cur]);
+                        S* dst = static_cast<S*>(c->buf[1 - c->cur]);
+                        dispatch(c, [&](auto k) { step_fused2d<decltype(k)>(c, src, dst); });
+                        c->cur = 1 - c->cur;
+                    }
+                    c->steps += 2 * kFuseSteps;
+                }
+            }
+        }
+        for (; i < n; ++i) {
             if (c->aa) {
                 S* A = static_cast<S*>(c->buf[0]);
                 const bool odd = c->steps & 1;

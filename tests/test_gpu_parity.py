@@ -37,6 +37,7 @@ CASES_3D = [
     (W.D2Q9, (70, 33, 1), 0.8, (0, 1, 0), (1e-5, 0, 0), 40, "channel"),
     (W.D2Q9, (300, 45, 1), 1.2, (2, 0, 0), (0, 1e-5, 0), 30, "channel"),
     (W.D2Q9, (64, 64, 1), 0.8, (0, 0, 0), (0, 0, 0), 50, "tg"),
+    (W.D2Q9, (45, 37, 1), 0.7, (0, 0, 0), (1e-5, -2e-5, 0), 21, "tg"),
 ]
 
 
@@ -157,6 +158,35 @@ def test_two_node_kernels_ab_equals_aa_bitwise_and_oracle(lattice, dims, force, 
                                   compressible=comp)
     assert rel_err(ab.get_populations().cpu().numpy(), f_or) <= TOL
     assert rel_err(ab.moments()[1].cpu().numpy(), u_or) <= TOL
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("dims", [(128, 128, 1), (130, 97, 1), (7, 5, 1), (1, 1, 1), (3, 40, 1),
+                                  (514, 2048, 1)], ids=lambda d: f"{d[0]}x{d[1]}")
+@pytest.mark.parametrize("force,comp", [((0, 0, 0), False), ((1e-5, -2e-5, 0), False),
+                                        ((1e-5, 0, 0), True)], ids=["plain", "force", "comp"])
+def test_fused_d2q9_launches_equal_one_step_launches(storage, dims, force, comp):
+    """A periodic D2Q9 two-lattice lbm_step(n) runs launches of four steps
+    (16 x 16 regions in LDS, inner 8 x 8 nodes stored) in pairs and the
+    remainder one step per launch; lbm_step(1) always launches one step.
+    The states agree bit for bit after 8, 13 and 16 steps: on ragged boxes,
+    boxes smaller than a region (wrapped several times), a box of 2^20 nodes
+    (whose one-step launches use the two-node kernel) and every storage,
+    where each fused step rounds through the storage type."""
+    print(f"fused D2Q9 {dims} {storage} F={force} comp={comp}", flush=True)
+    rho, u, noise = inputs(W.D2Q9, dims, "channel", seed=21, noise_amp=1e-5, bc=(0, 0, 0), U0=0.03)
+    fused = lbm.LBM(lbm.D2Q9, *dims, 0.7, force=force, storage=storage, compressible=comp)
+    single = lbm.LBM(lbm.D2Q9, *dims, 0.7, force=force, storage=storage, compressible=comp)
+    for s in (fused, single):
+        s.init_equilibrium(rho, u, noise)
+    for n in (8, 13, 16):
+        fused.step(n)
+        for _ in range(n):
+            single.step(1)
+        assert fused.steps_taken == single.steps_taken
+        assert torch.equal(fused.get_populations(), single.get_populations())
+    fused.close()
+    single.close()
 
 
 def test_translation_equivariance_bitwise():

@@ -167,7 +167,12 @@ lbm_status lbm_init_equilibrium(lbm_ctx* ctx, const double* rho, const double* u
 lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f);
 lbm_status lbm_get_populations(lbm_ctx* ctx, double* f);
 
-/* Advances n >= 0 time steps.  Asynchronous on the bound stream. */
+/*
+ * Advances n >= 0 time steps.  Asynchronous on the bound stream.  A
+ * periodic D2Q9 two-lattice box runs eight steps at a time as two launches
+ * of four steps each (blocked in LDS) and the rest one launch per step;
+ * the state after any n is bit for bit that of n one-step launches.
+ */
 lbm_status lbm_step(lbm_ctx* ctx, int n);
 
 /*

@@ -129,9 +129,12 @@ struct Impl {
     template <class K>
     static void step_fused2d(lbm_ctx* c, const S* src, S* dst)
     {
-        const dim3 grid((c->nx + kFuseInner - 1) / kFuseInner, (c->ny + kFuseInner - 1) / kFuseInner, 1);
+        const long long blocks = (long long)((c->nx + kFuseInner - 1) / kFuseInner) *
+                                 ((c->ny + kFuseInner - 1) / kFuseInner);
+        dim3 grid;
+        const FuseMap m = fuse_plan(c->nx, c->ny, blocks >= kFuseXcdMinBlocks ? kFuseXcdTile : 0, &grid);
         hipLaunchKernelGGL((k_step_ab_fused2d<S, K::force, K::comp, kNtStores>), grid, c->block, 0, c->stream,
-                           src, dst, step_args<typename Store<S>::C>(c));
+                           src, dst, step_args<typename Store<S>::C>(c), m);
     }
 
     static lbm_status eager(lbm_ctx* c, int n)

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void k_adjoint_init_map(const typename Store<S
 }
 
 // Sums the per-workgroup slots in workgroup order (one workgroup).
-static __global__ __launch_bounds__(256) void k_adjoint_sum(const double* __restrict__ acc, size_t nblocks,
+[[maybe_unused]] static __global__ __launch_bounds__(256) void k_adjoint_sum(const double* __restrict__ acc, size_t nblocks,
                                                      double* __restrict__ out)
 {
     __shared__ double s[kAccSlots][256];
@@ -315,7 +315,7 @@ static __global__ __launch_bounds__(256) void k_adjoint_sum(const double* __rest
         for (int c = 0; c < kAccSlots; ++c) out[c] = s[c][0];
 }
 
-static __global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ p, size_t n)
+[[maybe_unused]] static __global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ p, size_t n)
 {
     const size_t i = blockIdx.x * size_t(256) + threadIdx.x;
     if (i < n) p[i] = 0.0;

@@ -927,7 +927,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const S* __r
 // Sums the block partials in block order with one block; out[0..3] = mass
 // (plus the fluid-node count for deviation storage), kinetic energy
 // (1/2) sum rho_m |u|^2, max |u|, non-finite count.
-static __global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partials,
+[[maybe_unused]] static __global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partials,
                                                                  int nblocks, int deviation,
                                                                  double* __restrict__ out)
 {
@@ -963,7 +963,7 @@ static __global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const do
 }
 
 // Sums slots 0..2 of the block partials in block order (one workgroup).
-static __global__ __launch_bounds__(kReduceThreads) void k_sum3(const double* __restrict__ partials,
+[[maybe_unused]] static __global__ __launch_bounds__(kReduceThreads) void k_sum3(const double* __restrict__ partials,
                                                          int nblocks, double* __restrict__ out)
 {
     __shared__ double s[3][kReduceThreads];

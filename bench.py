@@ -208,7 +208,7 @@ def run_small_2d(n=128, steps=1000, tau=0.8):
 
     rho, u = W.taylor_green_2d(n, U0=0.01)
     out = {"workload": f"D2Q9 {n}^2 periodic Taylor-Green, tau={tau}, {steps} steps, FP64 AB",
-           "kernel": "k_step_ab_fused2d (4 steps per launch)"}
+           "kernel": "k_step_ab_fused2d<16> (4 steps per launch, 16x16-node regions)"}
     for graph in (False, True):
         sim = lbm.LBM(lbm.D2Q9, n, n, 1, tau, graph=graph)
         best = None
@@ -254,7 +254,7 @@ def run_large_2d(n=4096, steps=200, warmup=40, tau=0.8):
     mlups = n * n * steps / (ms * 1e-3) / 1e6
     one_step_bound = HBM_PEAK_GBS * 1e3 / 144.0
     return {"workload": f"D2Q9 {n}^2 periodic Taylor-Green, tau={tau}, {steps} steps, FP64 AB",
-            "kernel": "k_step_ab_fused2d (4 steps per launch, XCD-aware placement)",
+            "kernel": "k_step_ab_fused2d<32> (4 steps per launch, 32x32-node regions)",
             "mlups": round(mlups, 1), "bytes_per_update_moved": 36,
             "one_step_hbm_bound_mlups": round(one_step_bound, 1),
             "vs_one_step_hbm_bound": round(mlups / one_step_bound, 3)}

@@ -125,16 +125,28 @@ struct Impl {
         return eager(c, n);
     }
 
-    // kFuseSteps steps of a periodic D2Q9 two-lattice box in one launch.
+    // kFuseSteps steps of a periodic D2Q9 two-lattice box in one launch:
+    // 32 x 32 regions on large boxes, 16 x 16 regions otherwise (XCD-aware
+    // placement from kFuseXcdMinBlocks blocks up); see fused2d.hpp.
     template <class K>
     static void step_fused2d(lbm_ctx* c, const S* src, S* dst)
     {
-        const long long blocks = (long long)((c->nx + kFuseInner - 1) / kFuseInner) *
-                                 ((c->ny + kFuseInner - 1) / kFuseInner);
+        constexpr int I32 = kFuseInnerOf<32>, I16 = kFuseInnerOf<16>;
+        const auto blocks = [&](int inner) {
+            return (long long)((c->nx + inner - 1) / inner) * ((c->ny + inner - 1) / inner);
+        };
+        const auto args = step_args<typename Store<S>::C>(c);
         dim3 grid;
-        const FuseMap m = fuse_plan(c->nx, c->ny, blocks >= kFuseXcdMinBlocks ? kFuseXcdTile : 0, &grid);
-        hipLaunchKernelGGL((k_step_ab_fused2d<S, K::force, K::comp, kNtStores>), grid, c->block, 0, c->stream,
-                           src, dst, step_args<typename Store<S>::C>(c), m);
+        if (blocks(I32) >= kFuseBigMinBlocks) {
+            const FuseMap m = fuse_plan(c->nx, c->ny, I32, 0, &grid);
+            hipLaunchKernelGGL((k_step_ab_fused2d<32, S, K::force, K::comp, kNtStores>), grid, c->block, 0,
+                               c->stream, src, dst, args, m);
+        } else {
+            const FuseMap m =
+                fuse_plan(c->nx, c->ny, I16, blocks(I16) >= kFuseXcdMinBlocks ? kFuseXcdTile : 0, &grid);
+            hipLaunchKernelGGL((k_step_ab_fused2d<16, S, K::force, K::comp, kNtStores>), grid, c->block, 0,
+                               c->stream, src, dst, args, m);
+        }
     }
 
     static lbm_status eager(lbm_ctx* c, int n)

@@ -162,7 +162,8 @@ def test_two_node_kernels_ab_equals_aa_bitwise_and_oracle(lattice, dims, force, 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
 @pytest.mark.parametrize("dims", [(128, 128, 1), (130, 97, 1), (7, 5, 1), (1, 1, 1), (3, 40, 1),
-                                  (200, 170, 1), (514, 2048, 1)], ids=lambda d: f"{d[0]}x{d[1]}")
+                                  (200, 170, 1), (3000, 200, 1), (514, 2048, 1)],
+                         ids=lambda d: f"{d[0]}x{d[1]}")
 @pytest.mark.parametrize("force,comp", [((0, 0, 0), False), ((1e-5, -2e-5, 0), False),
                                         ((1e-5, 0, 0), True)], ids=["plain", "force", "comp"])
 def test_fused_d2q9_launches_equal_one_step_launches(storage, dims, force, comp):
@@ -170,11 +171,12 @@ def test_fused_d2q9_launches_equal_one_step_launches(storage, dims, force, comp)
     (16 x 16 regions in LDS, inner 8 x 8 nodes stored) in pairs and the
     remainder one step per launch; lbm_step(1) always launches one step.
     The states agree bit for bit after 8, 13 and 16 steps: on ragged boxes,
-    boxes smaller than a region (wrapped several times), boxes of 512 and
-    more inner blocks (XCD-aware placement in tiles of 8 x 8 blocks, partial
-    tiles and padding workgroups), a box of 2^20 nodes (whose one-step
-    launches use the two-node kernel) and every storage, where each fused
-    step rounds through the storage type."""
+    boxes smaller than a region (wrapped several times), 16 x 16 regions in
+    XCD-aware tiles of 8 x 8 blocks (partial tiles, padding workgroups; 200 x
+    170), 32 x 32 regions of four nodes per work-item on large ragged boxes
+    (3000 x 200, and 514 x 2048, a box of 2^20 nodes whose one-step launches
+    use the two-node kernel), and every storage, where each fused step
+    rounds through the storage type."""
     print(f"fused D2Q9 {dims} {storage} F={force} comp={comp}", flush=True)
     rho, u, noise = inputs(W.D2Q9, dims, "channel", seed=21, noise_amp=1e-5, bc=(0, 0, 0), U0=0.03)
     fused = lbm.LBM(lbm.D2Q9, *dims, 0.7, force=force, storage=storage, compressible=comp)

@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--pattern", default="ab", choices=["ab", "aa"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the FP16-storage comparison line")
+                    help="skip the extra lines (FP16 storage, compressible model, the other "
+                         "pattern, adjoint, channels, sphere box, D2Q9 boxes)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-probe", action="store_true",

@@ -376,13 +376,14 @@ def test_context_stream_differs_from_the_current_stream():
     sim.close()
 
 
+@pytest.mark.parametrize("n", [128, 512])
 @pytest.mark.parametrize("aa", [False, True], ids=["AB", "AA"])
-def test_graph_replay_matches_eager_bitwise(aa):
+def test_graph_replay_matches_eager_bitwise(aa, n):
     """LBM_FLAG_GRAPH replays a captured 32-step graph: after step counts that
     mix replays, parity alignment and eager remainders -- with eager work
     (reductions, exports) between replays -- the state equals the eager run
-    bit for bit every time."""
-    n = 128
+    bit for bit every time.  Two-lattice D2Q9 graphs hold four-step launches
+    (16 x 16 regions at 128^2, 32 x 32 regions at 512^2)."""
     rho, u = W.taylor_green_2d(n, U0=0.01)
     g = lbm.LBM(lbm.D2Q9, n, n, 1, 0.8, aa=aa, graph=True)
     e = lbm.LBM(lbm.D2Q9, n, n, 1, 0.8, aa=aa)

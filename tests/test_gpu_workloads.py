@@ -161,7 +161,7 @@ def test_reduced_precision_taylor_green_512():
     n, steps, every, U0 = 512, 500, 10, 0.05
     rho, u0 = W.taylor_green_3d(n, U0=U0)
     noise = torch.from_numpy(W.population_noise(W.D3Q19, (n, n, n), 1e-6, seed=4)).cuda()
-    inputs = (torch.from_numpy(np.ascontiguousarray(rho)).cuda(), torch.from_numpy(u0).cuda(), noise)
+    inputs = (torch.from_numpy(np.array(rho, copy=True)).cuda(), torch.from_numpy(np.array(u0, copy=True)).cuda(), noise)
     ts, ke64, u64 = _tg_run(n, "f64", steps, every, inputs)
     r64 = _rate(ts, ke64)
     for storage in ("f32", "f16", "bf16"):

@@ -468,6 +468,39 @@ __device__ __forceinline__ void put_pair(double* p, Pair v)
     __builtin_nontemporal_store(__builtin_bit_cast(U32x4, v), reinterpret_cast<U32x4*>(p));
 }
 
+// The 16-byte stores of a wavefront whose work-items write their own nodes
+// (node index non-decreasing with the lane), issued as buffer stores that
+// carry the cache-policy bits nt | sc1 (gfx950 encoding 2 | 16): streaming,
+// written through at system scope.  Measured on MI355X, D3Q19 256^3 FP64:
+// 811 vs 830 us per step (+2.3 %) against non-temporal global stores; a
+// plain 16-byte copy 6.69 vs 6.48 TB/s.  The buffer resource is
+// wavefront-uniform: its base is the tile of the first active work-item
+// (the lowest node of the wavefront), so every work-item's offset is a
+// small non-negative byte count, and its record count ends at the end of
+// the stored state, so a store outside it would be dropped, not written.
+struct WaveStores {
+    static constexpr int kAux = 2 | 16;  // nt | sc1
+    __amdgpu_buffer_rsrc_t rs;
+    size_t b0;  // element index of the resource's base
+
+    template <int Q>
+    __device__ static WaveStores make(double* dst, unsigned own, const Dims& g)
+    {
+        const unsigned t0 = __builtin_amdgcn_readfirstlane(own >> g.S);
+        const size_t b0 = size_t(t0) * Q << g.S;
+        const size_t total = (size_t((g.N + (1u << g.S) - 1) >> g.S) * Q) << g.S;
+        const size_t bytes = (total - b0) * sizeof(double);
+        const unsigned records = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : unsigned(bytes);
+        return {__builtin_amdgcn_make_buffer_rsrc(dst + b0, 0, records, 0x00020000), b0};
+    }
+
+    __device__ void put(size_t slot, Pair v) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, v), rs,
+                                               unsigned((slot - b0) * sizeof(double)), 0, kAux);
+    }
+};
+
 // Lane i receives v of lane i - 1 (SHIFT = 0x138, wave_shr:1) or of lane
 // i + 1 (SHIFT = 0x130, wave_shl:1); the edge lane keeps its own v.
 template <int SHIFT>
@@ -525,9 +558,10 @@ __global__ LBM_STEP_BOUNDS void k_step_ab_pairs(const double* __restrict__ src,
     collide<L, double, FORCE, COMP, false>(f0, p.c);
     collide<L, double, FORCE, COMP, false>(f1, p.c);
     const unsigned own = unsigned(x0) + unsigned(g.nx) * (unsigned(y) + unsigned(g.ny) * unsigned(z));
+    const WaveStores ws = WaveStores::make<Q>(dst, own, g);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        put_pair(dst + slot<Q>(a, own, TS), Pair{f0[a], f1[a]});
+        ws.put(slot<Q>(a, own, TS), Pair{f0[a], f1[a]});
     });
 }
 
@@ -566,9 +600,10 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_even_pairs(double* __restrict__ A, Ste
     });
     collide<L, double, FORCE, COMP, false>(f0, p.c);
     collide<L, double, FORCE, COMP, false>(f1, p.c);
+    const WaveStores ws = WaveStores::make<Q>(A, own, g);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        put_pair(A + slot<Q>(Lattice<L>::opp(a), own, TS), Pair{f0[a], f1[a]});
+        ws.put(slot<Q>(Lattice<L>::opp(a), own, TS), Pair{f0[a], f1[a]});
     });
 }
 

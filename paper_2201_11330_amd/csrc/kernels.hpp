@@ -408,6 +408,64 @@ struct StepArgs {
     CollideArgs<C> c;
 };
 
+// Two FP64 populations of neighbouring nodes (x0, x0 + 1), moved as one
+// 16-byte access.
+typedef unsigned U32x4 __attribute__((ext_vector_type(4)));
+
+struct Pair {
+    double lo, hi;
+};
+
+// The stores of a wavefront whose work-items write their own nodes (node
+// index non-decreasing with the lane), issued as buffer stores that carry
+// the cache-policy bits nt | sc1 (gfx950 encoding 2 | 16): streaming,
+// written through at system scope.  Measured on MI355X, D3Q19 256^3: the
+// two-node FP64 step 811 vs 830 us (+2.3 %), the one-node FP64 step 835 vs
+// 862 us (+3.2 %), FP32 +1.2 %, FP16 unchanged, against non-temporal global
+// stores; a plain 16-byte copy 6.69 vs 6.48 TB/s.  The buffer resource is
+// wavefront-uniform: its base is the tile of the first active work-item
+// (the lowest node of the wavefront), so every work-item's offset is a
+// small non-negative byte count, and its record count ends at the end of
+// the stored state, so a store outside it would be dropped, not written.
+template <class S>
+struct WaveStores {
+    static constexpr int kAux = 2 | 16;  // nt | sc1
+    __amdgpu_buffer_rsrc_t rs;
+    size_t b0;  // element index of the resource's base
+
+    template <int Q>
+    __device__ static WaveStores make(S* dst, unsigned own, const Dims& g)
+    {
+        const unsigned t0 = __builtin_amdgcn_readfirstlane(own >> g.S);
+        const size_t b0 = size_t(t0) * Q << g.S;
+        const size_t total = (size_t((g.N + (1u << g.S) - 1) >> g.S) * Q) << g.S;
+        const size_t bytes = (total - b0) * sizeof(S);
+        const unsigned records = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : unsigned(bytes);
+        return {__builtin_amdgcn_make_buffer_rsrc(dst + b0, 0, records, 0x00020000), b0};
+    }
+
+    __device__ unsigned offset(size_t slot) const { return unsigned((slot - b0) * sizeof(S)); }
+
+    __device__ void put(size_t slot, S v) const
+    {
+        typedef unsigned U32x2 __attribute__((ext_vector_type(2)));
+        if constexpr (sizeof(S) == 8) {
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), rs, offset(slot), 0, kAux);
+        } else if constexpr (sizeof(S) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, offset(slot), 0, kAux);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), rs, offset(slot), 0,
+                                                  kAux);
+        }
+    }
+
+    __device__ void put(size_t slot, Pair v) const
+    {
+        static_assert(sizeof(S) == 8, "pairs of FP64 populations");
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, v), rs, offset(slot), 0, kAux);
+    }
+};
+
 // Fused pull-stream + bounce-back + collide (AB).
 template <int L, class S, bool WALLS, bool FORCE, bool COMP, bool NT>
 __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restrict__ dst,
@@ -433,10 +491,18 @@ __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restri
     });
     if constexpr (WALLS) nodal_fill<L>(p.g, x, y, z, f);
     collide<L, C, FORCE, COMP, Store<S>::kDeviation>(f, p.c);
-    static_for<Q>([&](auto ac) {
-        constexpr int a = decltype(ac)::value;
-        put<NT>(dst + slot<Q>(a, own, TS), Store<S>::save(f[a]));
-    });
+    if constexpr (NT) {
+        const auto ws = WaveStores<S>::template make<Q>(dst, own, p.g);
+        static_for<Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            ws.put(slot<Q>(a, own, TS), Store<S>::save(f[a]));
+        });
+    } else {
+        static_for<Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            put<false>(dst + slot<Q>(a, own, TS), Store<S>::save(f[a]));
+        });
+    }
 }
 
 // Fused step of a fully periodic FP64 box with two nodes per work-item
@@ -449,12 +515,6 @@ __global__ LBM_STEP_BOUNDS void k_step_ab(const S* __restrict__ src, S* __restri
 // reads that one element itself (periodic wrap).  Same arithmetic per node
 // as k_step_ab; 16-byte accesses measured 3 % faster for FP64 storage on
 // large boxes.  Needs an even nx; lanes per row BXL = 1 << bxl_shift.
-typedef unsigned U32x4 __attribute__((ext_vector_type(4)));
-
-struct Pair {
-    double lo, hi;
-};
-
 template <bool NT>
 __device__ __forceinline__ Pair get_pair(const double* p)
 {
@@ -468,38 +528,6 @@ __device__ __forceinline__ void put_pair(double* p, Pair v)
     __builtin_nontemporal_store(__builtin_bit_cast(U32x4, v), reinterpret_cast<U32x4*>(p));
 }
 
-// The 16-byte stores of a wavefront whose work-items write their own nodes
-// (node index non-decreasing with the lane), issued as buffer stores that
-// carry the cache-policy bits nt | sc1 (gfx950 encoding 2 | 16): streaming,
-// written through at system scope.  Measured on MI355X, D3Q19 256^3 FP64:
-// 811 vs 830 us per step (+2.3 %) against non-temporal global stores; a
-// plain 16-byte copy 6.69 vs 6.48 TB/s.  The buffer resource is
-// wavefront-uniform: its base is the tile of the first active work-item
-// (the lowest node of the wavefront), so every work-item's offset is a
-// small non-negative byte count, and its record count ends at the end of
-// the stored state, so a store outside it would be dropped, not written.
-struct WaveStores {
-    static constexpr int kAux = 2 | 16;  // nt | sc1
-    __amdgpu_buffer_rsrc_t rs;
-    size_t b0;  // element index of the resource's base
-
-    template <int Q>
-    __device__ static WaveStores make(double* dst, unsigned own, const Dims& g)
-    {
-        const unsigned t0 = __builtin_amdgcn_readfirstlane(own >> g.S);
-        const size_t b0 = size_t(t0) * Q << g.S;
-        const size_t total = (size_t((g.N + (1u << g.S) - 1) >> g.S) * Q) << g.S;
-        const size_t bytes = (total - b0) * sizeof(double);
-        const unsigned records = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : unsigned(bytes);
-        return {__builtin_amdgcn_make_buffer_rsrc(dst + b0, 0, records, 0x00020000), b0};
-    }
-
-    __device__ void put(size_t slot, Pair v) const
-    {
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, v), rs,
-                                               unsigned((slot - b0) * sizeof(double)), 0, kAux);
-    }
-};
 
 // Lane i receives v of lane i - 1 (SHIFT = 0x138, wave_shr:1) or of lane
 // i + 1 (SHIFT = 0x130, wave_shl:1); the edge lane keeps its own v.
@@ -558,7 +586,7 @@ __global__ LBM_STEP_BOUNDS void k_step_ab_pairs(const double* __restrict__ src,
     collide<L, double, FORCE, COMP, false>(f0, p.c);
     collide<L, double, FORCE, COMP, false>(f1, p.c);
     const unsigned own = unsigned(x0) + unsigned(g.nx) * (unsigned(y) + unsigned(g.ny) * unsigned(z));
-    const WaveStores ws = WaveStores::make<Q>(dst, own, g);
+    const auto ws = WaveStores<double>::make<Q>(dst, own, g);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         ws.put(slot<Q>(a, own, TS), Pair{f0[a], f1[a]});
@@ -600,7 +628,7 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_even_pairs(double* __restrict__ A, Ste
     });
     collide<L, double, FORCE, COMP, false>(f0, p.c);
     collide<L, double, FORCE, COMP, false>(f1, p.c);
-    const WaveStores ws = WaveStores::make<Q>(A, own, g);
+    const auto ws = WaveStores<double>::make<Q>(A, own, g);
     static_for<Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         ws.put(slot<Q>(Lattice<L>::opp(a), own, TS), Pair{f0[a], f1[a]});
@@ -700,10 +728,18 @@ __global__ LBM_STEP_BOUNDS void k_step_aa_even(S* __restrict__ A,
     });
     if constexpr (WALLS) nodal_fill<L>(p.g, x, y, z, f);
     collide<L, C, FORCE, COMP, Store<S>::kDeviation>(f, p.c);
-    static_for<Q>([&](auto ac) {
-        constexpr int a = decltype(ac)::value;
-        put<NT>(A + slot<Q>(Lattice<L>::opp(a), own, TS), Store<S>::save(f[a]));
-    });
+    if constexpr (NT) {
+        const auto ws = WaveStores<S>::template make<Q>(A, own, p.g);
+        static_for<Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            ws.put(slot<Q>(Lattice<L>::opp(a), own, TS), Store<S>::save(f[a]));
+        });
+    } else {
+        static_for<Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            put<false>(A + slot<Q>(Lattice<L>::opp(a), own, TS), Store<S>::save(f[a]));
+        });
+    }
 }
 
 // AA odd step: f_a(x) from slot abar of x - e_a (or slot a of x at a wall);

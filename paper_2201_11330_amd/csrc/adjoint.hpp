@@ -162,11 +162,12 @@ __global__ LBM_STEP_BOUNDS void k_adjoint_step(const S* __restrict__ g,
                 base = p.omega * P - (V[0] * u[0] + V[1] * u[1] + V[2] * u[2]);
             }
             const C keep = C(1) - p.omega;
+            const auto ws = WaveStores<C>::template make<Q>(lam_out, own, p.g);
             static_for<Q>([&](auto ac) {
                 constexpr int b = decltype(ac)::value;
                 constexpr int ex = kLattice<L>.e[b][0], ey = kLattice<L>.e[b][1], ez = kLattice<L>.e[b][2];
-                put<true>(lam_out + slot<Q>(b, own, TS),
-                          C(keep * ls[b] + base + (eterm<ex>(V[0]) + eterm<ey>(V[1]) + eterm<ez>(V[2]))));
+                ws.put(slot<Q>(b, own, TS),
+                       C(keep * ls[b] + base + (eterm<ex>(V[0]) + eterm<ey>(V[1]) + eterm<ez>(V[2]))));
             });
             part[0] = -double(p.omega) * double(p.omega) * double(tsum);
             for (int d = 0; d < kDim<L>; ++d)

@@ -172,6 +172,10 @@ __global__ __launch_bounds__(256) void k_step_ab_fused2d(const S* __restrict__ s
         const int ox = bx * I + ix, oy = by * I + iy;
         if (ox >= g.nx || oy >= g.ny) continue;
         const unsigned own = unsigned(ox) + unsigned(g.nx) * unsigned(oy);
+        // Non-temporal global stores: the nt | sc1 buffer stores of the
+        // one-step kernels measured slower here (128^2: 11,950 vs 12,500-
+        // 13,300 MLUPS; 4096^2: 83,900 vs 89,600-91,000), the written state
+        // being read again, largely from cache, by the next launch.
         static_for<Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             put<NT>(dst + slot<Q>(a, own, TS), Store<S>::save(f[j][a]));

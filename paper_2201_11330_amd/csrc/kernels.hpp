@@ -418,8 +418,8 @@ struct Pair {
 
 // The stores of a wavefront whose work-items write their own nodes (node
 // index non-decreasing with the lane), issued as buffer stores that carry
-// the cache-policy bits nt | sc1 (gfx950 encoding 2 | 16): streaming,
-// written through at system scope.  Measured on MI355X, D3Q19 256^3: the
+// the cache-policy bits nt | sc1 (gfx950 encoding 2 | 16): streaming, at
+// device scope (sc1 without sc0), so the store goes through the XCD's L2.  Measured on MI355X, D3Q19 256^3: the
 // two-node FP64 step 811 vs 830 us (+2.3 %), the one-node FP64 step 835 vs
 // 862 us (+3.2 %), FP32 +1.2 %, FP16 unchanged, against non-temporal global
 // stores; a plain 16-byte copy 6.69 vs 6.48 TB/s.  The buffer resource is

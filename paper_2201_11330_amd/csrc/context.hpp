@@ -38,7 +38,8 @@ inline size_t storage_size(lbm_storage s)
 // buffers and the AA parity to where they started).
 constexpr int kGraphSteps = 32;
 
-// Non-temporal stores (and unshared loads) in the step kernels.
+// Non-temporal stores (and unshared loads) in the step kernels; the stores
+// of a work-item's own nodes also carry the sc1 bit (WaveStores).
 constexpr bool kNtStores = true;
 
 struct Ops;

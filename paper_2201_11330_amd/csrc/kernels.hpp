@@ -281,10 +281,11 @@ __device__ __forceinline__ bool beyond_nodal(const Dims& g, int x, int y, int z,
 
 // Loads and stores of population elements.  NT marks an access
 // non-temporal (streamed, not kept in the caches): used for every store of
-// a step and for the loads whose cache lines no other lane of the workgroup
-// touches (directions with e_x = 0, whose 64-lane rows are 512-byte
-// aligned).  Loads shifted by one element along x share their boundary
-// lines with the neighbouring wavefront and stay cached.
+// a step (the stores of a work-item's own nodes also carry sc1, through
+// WaveStores below) and for the loads whose cache lines no other lane of
+// the workgroup touches (directions with e_x = 0, whose 64-lane rows are
+// 512-byte aligned).  Loads shifted by one element along x share their
+// boundary lines with the neighbouring wavefront and stay cached.
 template <class S>
 using Bits = std::conditional_t<sizeof(S) == 8, unsigned long long,
                                 std::conditional_t<sizeof(S) == 4, unsigned, unsigned short>>;

@@ -346,6 +346,109 @@ def test_moments_follow_postprocessing():
     assert np.abs(v - (j + F[:, None, None, None] / 2)).max() < 1e-17
 
 
+# Monitor (Sec. 3.6 Monitor listing): total mass, kinetic energy and the
+# largest speed over the fluid nodes.  The pins below use states whose
+# moments are known in closed form, so the sums have exact values; the
+# listing's own loop starts at its second node and takes |u| in two
+# dimensions, and neither quirk is a property of the method, so a skipped
+# node, a 2-D norm or a dropped 1/2 must fail here.
+
+
+@pytest.mark.parametrize("lattice,dims,bc", [
+    (oracle.D2Q9, (7, 5, 1), (0, 0, 0)),
+    (oracle.D3Q19, (5, 6, 4), (0, 0, 0)),
+    (oracle.D3Q19, (5, 7, 4), (0, 1, 0)),
+    (oracle.D3Q27, (4, 5, 6), (1, 0, 2)),
+])
+def test_monitor_of_a_uniform_flow(lattice, dims, bc):
+    """A uniform equilibrium of density rho and velocity u = (a, b, c) (every
+    component nonzero in 3D) has the moments rho and u at every fluid node
+    (Sec. 2.1: the equilibrium's zeroth and first moments), so the Monitor
+    must give mass = V rho, KE = (rho0/2) V |u|^2 with the 3-D norm and
+    max |u| = |u|, V the number of fluid nodes.  After periodic steps the
+    state is unchanged (Pin P3) and so are the three values."""
+    nx, ny, nz = dims
+    vel = np.array([0.031, -0.017, 0.0 if lattice == oracle.D2Q9 else 0.023])
+    rho0 = 1.07
+    s = oracle.Sim(lattice, nx, ny, nz, tau=0.7, bc=bc)
+    fluid = s.geometry()
+    V = int(fluid.sum())
+    assert V < nx * ny * nz or bc == (0, 0, 0)
+    u = np.zeros((3, nz, ny, nx))
+    u[:, fluid] = vel[:, None]
+    s.init_equilibrium(np.full((nz, ny, nx), rho0), u)
+    speed = math.sqrt(float(vel @ vel))
+    steps = [0, 3] if bc == (0, 0, 0) else [0]
+    for n in steps:
+        s.step(n)
+        red = s.reduce()
+        assert abs(red["mass"] - V * rho0) <= 1e-14 * V * rho0
+        assert abs(red["ke"] - 0.5 * V * speed * speed) <= 1e-13 * V * speed * speed
+        assert abs(red["umax"] - speed) <= 1e-14 * speed
+        assert red["nonfinite"] == 0
+
+
+def test_monitor_of_the_compressible_uniform_flow():
+    """With the compressible equilibrium (Eq. (feq)) the kinetic energy is
+    sum (rho/2)|u|^2: a uniform flow at rho = 1.5 gives 1.5 times the
+    incompressible model's (rho0/2) V |u|^2, which the incompressible form of
+    the sum would miss."""
+    dims = (5, 4, 6)
+    nx, ny, nz = dims
+    vel = np.array([0.02, 0.015, -0.03])
+    speed2 = float(vel @ vel)
+    out = {}
+    for comp, r in ((True, 1.5), (False, 1.5), (True, 0.6)):
+        s = oracle.Sim(oracle.D3Q19, nx, ny, nz, tau=0.8, compressible=comp)
+        u = np.broadcast_to(vel[:, None, None, None], (3, nz, ny, nx))
+        s.init_equilibrium(np.full((nz, ny, nx), r), u)
+        s.step(2)
+        out[(comp, r)] = red = s.reduce()
+        V = nx * ny * nz
+        want = 0.5 * (r if comp else 1.0) * V * speed2
+        assert abs(red["ke"] - want) <= 1e-13 * want
+        assert abs(red["mass"] - r * V) <= 1e-14 * r * V
+        assert abs(red["umax"] - math.sqrt(speed2)) <= 1e-14 * math.sqrt(speed2)
+    assert abs(out[(True, 1.5)]["ke"] / out[(False, 1.5)]["ke"] - 1.5) < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16), (16, 12, 8), (12, 20, 4)])
+def test_monitor_of_the_taylor_green_start(dims):
+    """The 3D Taylor-Green start u = U0 sin x cos y cos z, v = -U0 cos x
+    sin y cos z, w = 0 on grids of n_i >= 3 nodes per axis: since
+    sum_i sin^2(2 pi i/n) = sum_i cos^2(2 pi i/n) = n/2 and
+    sum_i cos(4 pi i/n) = 0, the grid sums are exactly
+    KE = (1/2) sum (u^2 + v^2) = U0^2 nx ny nz / 8 and mass = nx ny nz, and
+    with every n_i divisible by 4 the largest speed is U0 (attained at
+    x = pi/2, y = z = 0; sin^2 x cos^2 y + cos^2 x sin^2 y <= 1)."""
+    nx, ny, nz = dims
+    U0 = 0.05
+    rho, u = W.taylor_green_3d(nx, ny, nz, U0=U0)
+    s = oracle.Sim(oracle.D3Q19, nx, ny, nz, tau=0.6)
+    s.init_equilibrium(rho, u)
+    red = s.reduce()
+    V = nx * ny * nz
+    assert abs(red["ke"] - U0 * U0 * V / 8) <= 1e-13 * U0 * U0 * V
+    assert abs(red["mass"] - V) <= 1e-14 * V
+    assert abs(red["umax"] - U0) <= 1e-14 * U0
+
+
+def test_monitor_counts_non_finite_populations():
+    """The Monitor's non-finite count is the number of NaN or infinite
+    populations on fluid nodes."""
+    dims = (4, 5, 3)
+    nx, ny, nz = dims
+    s = oracle.Sim(oracle.D3Q19, nx, ny, nz, tau=0.7, bc=(0, 1, 0))
+    rho, u = np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx))
+    s.init_equilibrium(rho, u)
+    f = s.get_populations()
+    f[3, 1, 2, 1] = np.nan
+    f[7, 2, 3, 0] = np.inf
+    f[11, 0, 0, 2] = np.nan  # a solid node (row y = 0): not counted
+    s.set_populations(f)
+    assert s.reduce()["nonfinite"] == 2
+
+
 def _ke_rate(lattice, dims, tau, steps, rho, u, every=10, skip=100):
     s = oracle.Sim(lattice, *dims, tau=tau)
     s.init_equilibrium(rho, u)

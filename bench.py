@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of the population buffer size "
                          "(reference point for HBM byte counters)")
+    ap.add_argument("--only", choices=sorted(EXTRA_LINES),
+                    help="run just this extra line (no main line, no CPU baseline) and print "
+                         "its JSON object")
     return ap.parse_args()
 
 
@@ -157,6 +160,122 @@ def run_channel(steps=200, warmup=10, nx=512, ny=128, nz=128, tau=0.9, g=1e-6, n
                         f"FP64 AB, {steps} steps",
             "mlups": round(mlups, 1), "mlups_fluid_nodes": round(mlups * fluid / ny, 1),
             "achieved_gbs": round(304 * nodes * steps / (ms * 1e-3) / 1e9, 1)}
+
+
+def run_channel_sustained(steps=20000, chunk=1000, warmup=10, nx=512, ny=128, nz=128, tau=0.9,
+                          g=1e-6):
+    """The channel workload at its stated length: 20,000 steps of the
+    512 x 128 x 128 box (halfway walls, g_x = 1e-6, tau = 0.9), issued as
+    lbm_step(chunk) calls with an event on the launch stream after each, so
+    that the throughput of every chunk shows how it changes over the run."""
+    import torch
+
+    from paper_2201_11330_amd import lbm
+    from paper_2201_11330_amd import workloads as W
+
+    bc = (W.PERIODIC, W.SOLID_ENDS, W.PERIODIC)
+    rho, u = W.channel(nx, ny, nz, amplitude=1e-4, seed=3, bc=bc)
+    sim = lbm.LBM(lbm.D3Q19, nx, ny, nz, tau, force=(g, 0.0, 0.0), bc=bc)
+    sim.init_equilibrium(rho, u)
+    del rho, u
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    nchunks = steps // chunk
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nchunks + 1)]
+    wall0 = time.perf_counter()
+    ev[0].record(sim.stream)
+    for i in range(nchunks):
+        sim.step(chunk)
+        ev[i + 1].record(sim.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    sim.close()
+    nodes = nx * ny * nz
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(nchunks)]
+    per = [nodes * chunk / (m * 1e-3) / 1e6 for m in ms]
+    total = sum(ms)
+    mlups = nodes * chunk * nchunks / (total * 1e-3) / 1e6
+    return {"workload": f"D3Q19 {nx}x{ny}x{nz} channel, solid planes y=0,{ny - 1}, g_x={g}, "
+                        f"tau={tau}, FP64 AB, {chunk * nchunks} steps ({nchunks} x lbm_step({chunk}))",
+            "mlups": round(mlups, 1),
+            "achieved_gbs": round(304 * nodes * chunk * nchunks / (total * 1e-3) / 1e9, 1),
+            "frac": round(304 * nodes * chunk * nchunks / (total * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "us_per_step": round(total * 1e3 / (chunk * nchunks), 2),
+            "chunk_mlups_first_last": [round(per[0], 1), round(per[-1], 1)],
+            "chunk_mlups_min_max": [round(min(per), 1), round(max(per), 1)],
+            "wall_s": round(wall, 3)}
+
+
+def _tg_decay(n, storage, steps, every, rho, u, noise, tau=0.6):
+    """One Taylor-Green run sampled every `every` steps: kinetic energies,
+    summed step time (an event pair around each lbm_step(every)) and the
+    final velocity."""
+    import torch
+
+    from paper_2201_11330_amd import lbm
+
+    sim = lbm.LBM(lbm.D3Q19, n, n, n, tau, storage=storage)
+    sim.init_equilibrium(rho, u, noise)
+    ts, ke, ms = [], [], 0.0
+    for it in range(0, steps + 1, every):
+        ts.append(it)
+        ke.append(sim.reduce()["ke"])
+        if it < steps:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(sim.stream)
+            sim.step(every)
+            e1.record(sim.stream)
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+    _, uN = sim.moments(dtype=torch.float32 if storage != "f64" else torch.float64)
+    sim.close()
+    return ts, ke, ms, uN
+
+
+def ke_decay_rate(ts, ke, skip=100):
+    """Least-squares slope of -ln KE(t) over the samples with t >= skip (the
+    first steps carry the start-up transient of the equilibrium start)."""
+    import numpy as np
+
+    ts, ke = np.asarray(ts, float), np.asarray(ke, float)
+    m = ts >= skip
+    return float(-np.polyfit(ts[m], np.log(ke[m]), 1)[0])
+
+
+def run_precision(n=512, steps=500, every=10, U0=0.05, tau=0.6):
+    """Reduced-precision workload: D3Q19 n^3 Taylor-Green, tau = 0.6, 500
+    steps, populations stored as f - w in FP16 and BF16 (and FP32) with FP32
+    arithmetic, each against the FP64 run on the same inputs (population
+    noise U(+-1e-6) from torch's seeded device generator, seed 4): MLUPS of
+    the steps, max |u - u_f64| and the relative error of the kinetic-energy
+    decay rate (KE sampled every 10 steps, fitted from step 100)."""
+    import torch
+
+    from paper_2201_11330_amd import workloads as W
+
+    rho, u = W.taylor_green_3d(n, U0=U0)
+    rho = torch.from_numpy(rho).cuda()
+    u = torch.from_numpy(u).cuda()
+    noise = W.uniform_noise_device((19, n, n, n), 1e-6, seed=4)
+    nodes = n ** 3
+    out = {"workload": f"D3Q19 {n}^3 periodic 3D Taylor-Green U0={U0} + 1e-6 noise (device "
+                       f"generator, seed 4), tau={tau}, {steps} steps, KE every {every} steps"}
+    ts, ke64, ms64, u64 = _tg_decay(n, "f64", steps, every, rho, u, noise, tau)
+    r64 = ke_decay_rate(ts, ke64)
+    m64 = nodes * steps / (ms64 * 1e-3) / 1e6
+    out["f64"] = {"mlups": round(m64, 1), "ke_decay_rate_per_step": r64}
+    for storage in ("f16", "bf16", "f32"):
+        ts, ke, ms, us = _tg_decay(n, storage, steps, every, rho, u, noise, tau)
+        du = (us.to(torch.float64) - u64).abs().max().item()
+        del us
+        torch.cuda.empty_cache()
+        m = nodes * steps / (ms * 1e-3) / 1e6
+        blu = 2 * 19 * STORAGE_BYTES[storage]
+        out[storage] = {"mlups": round(m, 1), "speedup_vs_f64": round(m / m64, 3),
+                        "frac": round(m * blu / 1e3 / HBM_PEAK_GBS, 4),
+                        "ke_decay_rate_rel_err": abs(ke_decay_rate(ts, ke) / r64 - 1),
+                        "max_abs_du": du, "max_abs_du_over_U0": du / U0}
+    return out
 
 
 def run_paper_sphere(steps=100, warmup=5, storage="f64"):
@@ -325,12 +444,21 @@ def step_kernel_name(n, storage, pattern):
 
 
 def kernel_sources_sha256():
-    """Hash of the sources that define the step kernels (device code)."""
-    parts = ["paper_2201_11330_amd/csrc/kernels.hpp", "paper_2201_11330_amd/csrc/lattice.hpp"]
+    """Hash of everything that decides the code and launch of the step
+    kernels: every source of the library (device code, launch plan, store
+    policy) and the compiler flags."""
+    from paper_2201_11330_amd import build as hip_build
+
+    csrc = os.path.join(ROOT, "paper_2201_11330_amd", "csrc")
+    parts = [os.path.join("paper_2201_11330_amd", "csrc", f) for f in sorted(os.listdir(csrc))
+             if f.endswith((".hpp", ".hip"))]
+    parts.append(os.path.join("include", "lbm.h"))
     h = hashlib.sha256()
     for p in parts:
+        h.update(p.encode())
         with open(os.path.join(ROOT, p), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(hip_build.HIPCC_FLAGS).encode())
     return h.hexdigest()
 
 
@@ -404,6 +532,58 @@ def host_cpu_model():
     return None
 
 
+def line_fp16(args, mlups):
+    """FP16 storage (f - w) of the main workload.  Its launches are short
+    (~205 us): 300 untimed steps (~60 ms) let the clocks settle first."""
+    n = args.n
+    r = run_gpu(n, "f16", args.pattern, args.steps, max(args.warmup, 300))
+    m = n ** 3 * args.steps / (r["total_ms"] * 1e-3) / 1e6
+    a = 2 * 19 * 2 * n ** 3 / (r["launch_ms_mean"] * 1e-3) / 1e9
+    return {"kernel": step_kernel_name(n, "f16", args.pattern), "warmup": max(args.warmup, 300),
+            "mlups": round(m, 1), "speedup_vs_f64": round(m / mlups, 3) if mlups else None,
+            "launch_ms_mean": round(r["launch_ms_mean"], 5), "achieved_gbs": round(a, 1),
+            "frac": round(a / HBM_PEAK_GBS, 4)}
+
+
+def line_compressible(args, mlups):
+    n = args.n
+    r = run_gpu(n, "f64", args.pattern, args.steps, args.warmup, compressible=True)
+    m = n ** 3 * args.steps / (r["total_ms"] * 1e-3) / 1e6
+    a = 304 * n ** 3 / (r["launch_ms_mean"] * 1e-3) / 1e9
+    return {"workload": "as the main line with the compressible equilibrium of Eq. (feq)",
+            "mlups": round(m, 1), "vs_incompressible": round(m / mlups, 3) if mlups else None,
+            "launch_ms_mean": round(r["launch_ms_mean"], 5), "achieved_gbs": round(a, 1),
+            "frac": round(a / HBM_PEAK_GBS, 4)}
+
+
+def line_other_pattern(args, mlups):
+    n = args.n
+    other = "aa" if args.pattern == "ab" else "ab"
+    r = run_gpu(n, "f64", other, args.steps, args.warmup)
+    m = n ** 3 * args.steps / (r["total_ms"] * 1e-3) / 1e6
+    a = 304 * n ** 3 / (r["launch_ms_mean"] * 1e-3) / 1e9
+    return {"workload": f"as the main line, {other.upper()} pattern",
+            "kernel": step_kernel_name(n, "f64", other), "mlups": round(m, 1),
+            "launch_ms_mean": round(r["launch_ms_mean"], 5), "achieved_gbs": round(a, 1),
+            "frac": round(a / HBM_PEAK_GBS, 4)}
+
+
+# Extra lines of the default run, in order (name -> fn(args, main-line MLUPS)).
+EXTRA_LINES = {
+    "fp16_store": line_fp16,
+    "compressible": line_compressible,
+    "aa_pattern": line_other_pattern,
+    "precision_512": lambda args, mlups: run_precision(),
+    "adjoint": lambda args, mlups: run_adjoint(),
+    "channel": lambda args, mlups: run_channel(),
+    "channel_sustained": lambda args, mlups: run_channel_sustained(),
+    "channel_nodal": lambda args, mlups: run_channel(nodal=True),
+    "paper_sphere_d3q27": lambda args, mlups: run_paper_sphere(),
+    "small_2d": lambda args, mlups: run_small_2d(),
+    "large_2d": lambda args, mlups: run_large_2d(),
+}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -415,6 +595,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.only:
+        print(json.dumps({args.only: EXTRA_LINES[args.only](args, None)}), flush=True)
+        return
     n = args.n
     r = run_gpu(n, args.storage, args.pattern, args.steps, args.warmup, args.copy_probe)
     nodes = n ** 3
@@ -429,6 +612,11 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r["total_ms"] / args.steps, 5),
+        # value and ms_per_step: the K launches and the closing Monitor
+        # reduction; roofline: the K launches alone (launch gaps included).
+        "timing": {"steps_ms": round(r["launch_ms_mean"] * args.steps, 4),
+                   "monitor_ms": round(r["total_ms"] - r["launch_ms_mean"] * args.steps, 4),
+                   "mlups_steps_only": round(nodes / (r["launch_ms_mean"] * 1e-3) / 1e6, 1)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -457,36 +645,8 @@ def main():
     if "copy_probe" in r:
         out["copy_probe"] = r["copy_probe"]
     if not args.no_extras and args.storage == "f64":
-        # The FP16 launches are short (~205 us): 300 untimed steps (~60 ms)
-        # so that the GPU clocks have settled before the timed region.
-        r16 = run_gpu(n, "f16", args.pattern, args.steps, max(args.warmup, 300))
-        m16 = nodes * args.steps / (r16["total_ms"] * 1e-3) / 1e6
-        a16 = 2 * 19 * 2 * nodes / (r16["launch_ms_mean"] * 1e-3) / 1e9
-        out["fp16_store"] = {"mlups": round(m16, 1), "speedup_vs_f64": round(m16 / mlups, 3),
-                             "achieved_gbs": round(a16, 1),
-                             "frac": round(a16 / HBM_PEAK_GBS, 4)}
-    if not args.no_extras and args.storage == "f64":
-        rc = run_gpu(n, "f64", args.pattern, args.steps, args.warmup, compressible=True)
-        mc = nodes * args.steps / (rc["total_ms"] * 1e-3) / 1e6
-        ac = blu * nodes / (rc["launch_ms_mean"] * 1e-3) / 1e9
-        out["compressible"] = {"workload": "as the main line with the compressible equilibrium "
-                                           "of Eq. (feq)",
-                               "mlups": round(mc, 1), "vs_incompressible": round(mc / mlups, 3),
-                               "achieved_gbs": round(ac, 1), "frac": round(ac / HBM_PEAK_GBS, 4)}
-        other = "aa" if args.pattern == "ab" else "ab"
-        ro = run_gpu(n, "f64", other, args.steps, args.warmup)
-        mo = nodes * args.steps / (ro["total_ms"] * 1e-3) / 1e6
-        ao = blu * nodes / (ro["launch_ms_mean"] * 1e-3) / 1e9
-        out[f"{other}_pattern"] = {"workload": f"as the main line, {other.upper()} pattern",
-                                   "kernel": step_kernel_name(n, "f64", other),
-                                   "mlups": round(mo, 1), "achieved_gbs": round(ao, 1),
-                                   "frac": round(ao / HBM_PEAK_GBS, 4)}
-        out["adjoint"] = run_adjoint()
-        out["channel"] = run_channel()
-        out["channel_nodal"] = run_channel(nodal=True)
-        out["paper_sphere_d3q27"] = run_paper_sphere()
-        out["small_2d"] = run_small_2d()
-        out["large_2d"] = run_large_2d()
+        for name, fn in EXTRA_LINES.items():
+            out[name] = fn(args, mlups)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     print(json.dumps(out), flush=True)

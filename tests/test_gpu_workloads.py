@@ -149,19 +149,27 @@ def _rate(ts, ke, skip=100):
     return -np.polyfit(ts[m], np.log(ke[m]), 1)[0]
 
 
+# Measured on MI355X (this workload, these inputs): max |u - u_f64| / U0 and
+# the relative KE decay-rate error of each storage.
+MEASURED_512 = {"f32": (9.7e-6, 1.0e-3), "f16": (2.24e-3, 5.8e-2), "bf16": (2.64e-2, 0.251)}
+
+
 @pytest.mark.slow
 def test_reduced_precision_taylor_green_512():
-    """Workload D3Q19 512^3 Taylor-Green, tau = 0.6, 500 steps: FP16 and BF16
-    storage of f - w (FP32 arithmetic) against the FP64 run on the same seed.
-    Reported: max |u| error (absolute and / U0) and the relative error of the
-    kinetic-energy decay rate (KE drops only ~1.5 % over the run, so a 1e-5
-    relative KE error is ~1e-3 of the rate).  Asserted loosely (parity
-    unpinned: no closed form; the FP64 run is itself pinned by the parity
-    tests)."""
+    """Workload D3Q19 512^3 Taylor-Green, tau = 0.6, 500 steps: FP32, FP16 and
+    BF16 storage of f - w (FP32 arithmetic) against the FP64 run on the same
+    inputs (population noise U(+-1e-6) from torch's device generator, seed 4,
+    as in the benchmark's precision line).  Reported: max |u| error
+    (absolute and / U0) and the relative error of the kinetic-energy decay
+    rate (KE drops only ~1.5 % over the run, so a 1e-5 relative KE error is
+    ~1e-3 of the rate).  There is no closed form (parity unpinned beyond the
+    FP64 run, which the parity tests pin); each error is bounded at 3x its
+    measured value, so a regression of that size fails."""
     n, steps, every, U0 = 512, 500, 10, 0.05
     rho, u0 = W.taylor_green_3d(n, U0=U0)
-    noise = torch.from_numpy(W.population_noise(W.D3Q19, (n, n, n), 1e-6, seed=4)).cuda()
-    inputs = (torch.from_numpy(np.array(rho, copy=True)).cuda(), torch.from_numpy(np.array(u0, copy=True)).cuda(), noise)
+    noise = W.uniform_noise_device((19, n, n, n), 1e-6, seed=4)
+    inputs = (torch.from_numpy(np.array(rho, copy=True)).cuda(),
+              torch.from_numpy(np.array(u0, copy=True)).cuda(), noise)
     ts, ke64, u64 = _tg_run(n, "f64", steps, every, inputs)
     r64 = _rate(ts, ke64)
     for storage in ("f32", "f16", "bf16"):
@@ -172,8 +180,8 @@ def test_reduced_precision_taylor_green_512():
               f"KE decay rate error {rerr:.3e} (FP64 rate {r64:.6e}/step)")
         del u
         torch.cuda.empty_cache()
-        bound = {"f32": (1e-4, 1e-2), "f16": (5e-2, 1.0), "bf16": (0.25, 10.0)}[storage]
-        assert du / U0 < bound[0] and rerr < bound[1]
+        m_du, m_rate = MEASURED_512[storage]
+        assert du / U0 < 3 * m_du and rerr < 3 * m_rate
 
 
 @pytest.mark.slow

@@ -195,6 +195,26 @@ lbm_status lbm_moments(lbm_ctx* ctx, void* rho, void* u, int out_is_f32);
 lbm_status lbm_reduce(lbm_ctx* ctx, double* mass, double* kinetic_energy, double* umax);
 
 /*
+ * lbm_reduce for callers that cannot allocate memory or wait on the stream
+ * (code under HIP graph capture, tight serving loops): the same Monitor
+ * reduction, with the same kernels and summation order, so the results are
+ * bit for bit those of lbm_reduce.  It calls no allocating routine and does
+ * not synchronise: the per-workgroup partials go to a library-owned static
+ * device array of 5 * 1024 + 4 doubles (41 KiB) per device, held until the
+ * process ends, which is enough for every box lbm_create accepts (the
+ * reduction runs a fixed grid of 1024 workgroups over the box).  result:
+ * device FP64 [4] written asynchronously on the bound stream with mass,
+ * kinetic energy, max |u| and the number of non-finite populations (the
+ * caller checks the last one; there is no LBM_EUNSTABLE here).  The current
+ * device must be the one the context was bound on (LBM_EINVAL otherwise).
+ * Every call on a device shares that device's array, which keeps the last
+ * call's partials: calls whose reductions overlap on one device (different
+ * streams, or threads) race and may return mixed results; calls ordered on
+ * one stream do not.
+ */
+lbm_status lbm_reduce_noalloc(lbm_ctx* ctx, double* result);
+
+/*
  * SetGeometry with a solid mask (Sec. 3.3: the geo array marks fluid and
  * solid nodes): solid[id] != 0 makes node id solid, in addition to the solid
  * end planes of LBM_SOLID_ENDS axes.  Every link from a fluid node into a

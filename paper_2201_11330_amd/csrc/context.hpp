@@ -64,6 +64,7 @@ struct lbm_ctx {
     int nodal = -1;     // axis with LBM_WALLS_NODAL, or -1
 
     bool bound = false;
+    int device = -1;  // current device at lbm_bind
     void* buf[2] = {nullptr, nullptr};
     int cur = 0;  // AB: buffer holding the current state
     hipStream_t stream = nullptr;
@@ -97,7 +98,7 @@ struct Ops {
                          const double* noise);
     lbm_status (*export_f)(lbm_ctx*, double* f);
     lbm_status (*moments)(lbm_ctx*, void* rho, void* u, int f32);
-    lbm_status (*reduce)(lbm_ctx*);
+    lbm_status (*reduce)(lbm_ctx*, double* partials);  // partials: 5 kReduceBlocks + 4 doubles
     lbm_status (*adjoint)(lbm_ctx*, int n, int k, const void* ckpt, void* ws, const double* rho0,
                           const double* u0, const double* ubar, double* u0bar, double* out4);
     lbm_status (*build_links)(lbm_ctx*, const unsigned char* mask);

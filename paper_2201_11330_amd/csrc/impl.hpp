@@ -353,19 +353,21 @@ struct Impl {
         return LBM_OK;
     }
 
-    static lbm_status reduce(lbm_ctx* c)
+    // Monitor reduction into partials (5 kReduceBlocks + 4 doubles; the last
+    // four receive mass, kinetic energy, max |u| and the non-finite count).
+    static lbm_status reduce(lbm_ctx* c, double* partials)
     {
         IoArgs p = io_args(c);
         const S* A = static_cast<const S*>(c->buf[c->cur]);
         if (c->walls)
             hipLaunchKernelGGL((k_reduce_partials<L, S, true>), dim3(kReduceBlocks),
-                               dim3(kReduceThreads), 0, c->stream, A, c->d_partials, p);
+                               dim3(kReduceThreads), 0, c->stream, A, partials, p);
         else
             hipLaunchKernelGGL((k_reduce_partials<L, S, false>), dim3(kReduceBlocks),
-                               dim3(kReduceThreads), 0, c->stream, A, c->d_partials, p);
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, c->stream, c->d_partials,
+                               dim3(kReduceThreads), 0, c->stream, A, partials, p);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, c->stream, partials,
                            kReduceBlocks, int(Store<S>::kDeviation),
-                           c->d_partials + 5 * size_t(kReduceBlocks));
+                           partials + 5 * size_t(kReduceBlocks));
         LBM_HIP(hipGetLastError());
         return LBM_OK;
     }

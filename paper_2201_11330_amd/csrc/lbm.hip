@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "context.hpp"
@@ -130,6 +131,35 @@ lbm_status check_device_ptr(const void* p, const char* name, bool allow_null, si
     return LBM_OK;
 }
 
+// Device scratch of lbm_reduce_noalloc: the Monitor's per-workgroup
+// partials (5 doubles for each of the kReduceBlocks workgroups, which stride
+// over the whole box, so every box size fits) and the 4 results.  Each device
+// holds its own copy until the process ends; calls on one device share it.
+constexpr size_t kScratchDoubles = 5 * size_t(kReduceBlocks) + 4;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// Device address of `scratch` per device, looked up once per device by the
+// first lbm_reduce_noalloc call made with that device current.  In host code
+// the name `scratch` is only a host-side stand-in; kernels get this address.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_addr[kMaxDevices] = {};
+
+lbm_status scratch_address(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EINVAL, "device %d outside [0, %d)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(LBM_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_addr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_addr[dev];
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -230,6 +260,8 @@ lbm_status lbm_bind(lbm_ctx* c, void* buf_a, void* buf_b, void* hip_stream)
     }
     if ((reinterpret_cast<uintptr_t>(buf_a) | reinterpret_cast<uintptr_t>(buf_b)) & 255)
         return fail(LBM_EINVAL, "population buffers must be 256-byte aligned");
+    int dev = -1;
+    LBM_HIP(hipGetDevice(&dev));
     LBM_HIP(hipMalloc(&c->d_partials, sizeof(double) * (5 * size_t(kReduceBlocks) + 4)));
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->h_result), 4 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -241,6 +273,7 @@ lbm_status lbm_bind(lbm_ctx* c, void* buf_a, void* buf_b, void* hip_stream)
     c->buf[1] = buf_b;
     c->cur = 0;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    c->device = dev;
     c->bound = true;
     c->state_valid = false;
     return LBM_OK;
@@ -306,7 +339,7 @@ lbm_status lbm_reduce(lbm_ctx* c, double* mass, double* kinetic_energy, double* 
 {
     lbm_status st = need_state(c);
     if (st) return st;
-    if ((st = c->ops->reduce(c))) return st;
+    if ((st = c->ops->reduce(c, c->d_partials))) return st;
     LBM_HIP(hipMemcpyAsync(c->h_result, c->d_partials + 5 * size_t(kReduceBlocks), 4 * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
     LBM_HIP(hipStreamSynchronize(c->stream));
@@ -315,6 +348,29 @@ lbm_status lbm_reduce(lbm_ctx* c, double* mass, double* kinetic_energy, double* 
     if (umax) *umax = c->h_result[2];
     if (c->h_result[3] != 0.0 || !std::isfinite(c->h_result[0]) || !std::isfinite(c->h_result[1]))
         return fail(LBM_EUNSTABLE, "%.0f non-finite populations", c->h_result[3]);
+    return LBM_OK;
+}
+
+lbm_status lbm_reduce_noalloc(lbm_ctx* c, double* result)
+{
+    lbm_status st = need_state(c);
+    if (st) return st;
+    static_assert(kScratchDoubles >= 5 * size_t(kReduceBlocks) + 4, "scratch too small for the partials");
+    const size_t need = 5 * size_t(kReduceBlocks) + 4;  // the same for every box size
+    if (need > kScratchDoubles)
+        return fail(LBM_EINVAL, "the reduction needs %zu doubles of scratch, the maximum is %zu", need,
+                    kScratchDoubles);
+    if ((st = check_device_ptr(result, "result", false, 4 * sizeof(double)))) return st;
+    int dev = -1;
+    LBM_HIP(hipGetDevice(&dev));
+    if (dev != c->device)
+        return fail(LBM_EINVAL, "current device %d is not the device %d the context was bound on", dev,
+                    c->device);
+    double* ptr = nullptr;
+    if ((st = scratch_address(dev, &ptr))) return st;
+    if ((st = c->ops->reduce(c, ptr))) return st;
+    LBM_HIP(hipMemcpyAsync(result, ptr + 5 * size_t(kReduceBlocks), 4 * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
     return LBM_OK;
 }
 

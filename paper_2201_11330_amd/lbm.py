@@ -29,7 +29,7 @@ Q_OF = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 EXPORTS = (
     "lbm_create", "lbm_buffer_bytes", "lbm_bind", "lbm_init_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments", "lbm_reduce",
-    "lbm_steps_taken", "lbm_set_solid", "lbm_wall_force", "lbm_forward_record",
+    "lbm_reduce_noalloc", "lbm_steps_taken", "lbm_set_solid", "lbm_wall_force", "lbm_forward_record",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint", "lbm_destroy", "lbm_status_string",
     "lbm_last_error",
 )
@@ -79,6 +79,8 @@ def lib():
     L.lbm_moments.restype = st
     L.lbm_reduce.argtypes = [vp, dp, dp, dp]
     L.lbm_reduce.restype = st
+    L.lbm_reduce_noalloc.argtypes = [vp, vp]
+    L.lbm_reduce_noalloc.restype = st
     L.lbm_steps_taken.argtypes = [vp]
     L.lbm_steps_taken.restype = ctypes.c_longlong
     L.lbm_set_solid.argtypes = [vp, vp]
@@ -314,6 +316,16 @@ class LBM:
         if st not in (OK, EUNSTABLE):
             check(st, "lbm_reduce")
         return out
+
+    def reduce_noalloc(self, result):
+        """Monitor into ``result`` (FP64 device tensor of 4: mass, kinetic
+        energy, max |u|, non-finite count), asynchronously on the stream;
+        allocates nothing (lbm_reduce_noalloc)."""
+        if result.dtype != torch.float64 or not result.is_cuda or not result.is_contiguous():
+            raise ValueError("result must be a contiguous FP64 device tensor")
+        self._enter(result)
+        check(lib().lbm_reduce_noalloc(self._h, _ptr(result)), "lbm_reduce_noalloc")
+        self._leave()
 
 
 class LBMRollout(torch.autograd.Function):

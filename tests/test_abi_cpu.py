@@ -116,6 +116,7 @@ def test_calls_before_bind_fail_without_device_work():
     d = ctypes.c_double()
     assert L.lbm_step(h, 1) == lbm.ENOTBOUND
     assert L.lbm_reduce(h, ctypes.byref(d), None, None) == lbm.ENOTBOUND
+    assert L.lbm_reduce_noalloc(h, None) == lbm.ENOTBOUND
     assert L.lbm_moments(h, None, None, 0) == lbm.ENOTBOUND
     assert L.lbm_get_populations(h, None) == lbm.ENOTBOUND
     assert L.lbm_set_populations(h, None) == lbm.ENOTBOUND

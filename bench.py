@@ -27,8 +27,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "MLUPS & % of HBM peak, D3Q19 256³ FP64 vs FP16-store; adjoint/forward ratio"
-STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
-DTYPE_NAME = {"f64": "f64", "f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32"}
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "e4m11": 2}
+DTYPE_NAME = {"f64": "f64", "f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32",
+              "e4m11": "e4m11-store/f32"}
 
 
 def parse():
@@ -264,7 +265,7 @@ def run_precision(n=512, steps=500, every=10, U0=0.05, tau=0.6):
     r64 = ke_decay_rate(ts, ke64)
     m64 = nodes * steps / (ms64 * 1e-3) / 1e6
     out["f64"] = {"mlups": round(m64, 1), "ke_decay_rate_per_step": r64}
-    for storage in ("f16", "bf16", "f32"):
+    for storage in ("f16", "e4m11", "bf16", "f32"):
         ts, ke, ms, us = _tg_decay(n, storage, steps, every, rho, u, noise, tau)
         du = (us.to(torch.float64) - u64).abs().max().item()
         del us
@@ -350,9 +351,9 @@ def run_small_2d(n=128, steps=1000, tau=0.8):
 
 def run_large_2d(n=4096, steps=200, warmup=40, tau=0.8):
     """D2Q9 n^2 periodic Taylor-Green (U0 = 0.01), FP64 AB: a box far larger
-    than the caches, where the four-step launches read and write the state
-    once per four steps (36 B per update) against the 144 B a one-step pass
-    moves."""
+    than the caches, where the four-step launches (strips streamed up the
+    rows) read and write the state once per four steps (36 B per update)
+    against the 144 B a one-step pass moves."""
     import torch
 
     from paper_2201_11330_amd import lbm
@@ -374,7 +375,8 @@ def run_large_2d(n=4096, steps=200, warmup=40, tau=0.8):
     mlups = n * n * steps / (ms * 1e-3) / 1e6
     one_step_bound = HBM_PEAK_GBS * 1e3 / 144.0
     return {"workload": f"D2Q9 {n}^2 periodic Taylor-Green, tau={tau}, {steps} steps, FP64 AB",
-            "kernel": "k_step_ab_fused2d<32> (4 steps per launch, 32x32-node regions)",
+            "kernel": "k_step_ab_stream2d (4 steps per launch, strips of 240 columns streamed "
+                      "up row segments)",
             "mlups": round(mlups, 1), "bytes_per_update_moved": 36,
             "one_step_hbm_bound_mlups": round(one_step_bound, 1),
             "vs_one_step_hbm_bound": round(mlups / one_step_bound, 3)}

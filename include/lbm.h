@@ -82,9 +82,20 @@ typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_lattice;
 /* Storage of the populations in device memory.  LBM_F64 stores f and
  * computes in FP64 (the paper's precision).  The others store the deviation
  * f_a - t_a and compute in FP32: LBM_F32 in FP32, LBM_F16_DEV in IEEE half,
- * LBM_BF16_DEV in bfloat16, each rounded to nearest-even on store.
- * Reductions accumulate in FP64 for every storage. */
-typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_DEV = 2, LBM_BF16_DEV = 3 } lbm_storage;
+ * LBM_BF16_DEV in bfloat16, LBM_E4M11_DEV in a 16-bit format with 4 exponent
+ * and 11 fraction bits (after the FP16C format of Lehmann et al., Phys. Rev.
+ * E 106, 015308 (2022): |f_a - t_a| < 1, so the exponent range of IEEE half
+ * is traded for one more fraction bit; normal numbers 2^-14 .. 0.99976,
+ * subnormals down to 2^-25, IEEE-style infinities and NaN; twice the
+ * precision of IEEE half everywhere below 1), each rounded to nearest-even
+ * on store.  Reductions accumulate in FP64 for every storage. */
+typedef enum {
+    LBM_F64 = 0,
+    LBM_F32 = 1,
+    LBM_F16_DEV = 2,
+    LBM_BF16_DEV = 3,
+    LBM_E4M11_DEV = 4
+} lbm_storage;
 
 /* Boundary of one axis. */
 typedef enum {

@@ -29,7 +29,8 @@ inline size_t storage_size(lbm_storage s)
     case LBM_F64: return 8;
     case LBM_F32: return 4;
     case LBM_F16_DEV:
-    case LBM_BF16_DEV: return 2;
+    case LBM_BF16_DEV:
+    case LBM_E4M11_DEV: return 2;
     }
     return 0;
 }

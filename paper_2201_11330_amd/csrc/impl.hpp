@@ -4,11 +4,13 @@
 
 #include "context.hpp"
 #include "fused2d.hpp"
+#include "stream2d.hpp"
 
 namespace imexlbm {
 
 // A captured run holds whole pairs of fused launches (see eager()).
 static_assert(kGraphSteps % (2 * kFuseSteps) == 0, "graph length must be a multiple of 2 * kFuseSteps");
+static_assert(kStreamLevels == kFuseSteps, "both multi-step launches take the same number of steps");
 
 // Compile-time configuration of the step kernels: walls or masks present,
 // body force, compressible equilibrium (which always takes the force path).
@@ -137,7 +139,16 @@ struct Impl {
         };
         const auto args = step_args<typename Store<S>::C>(c);
         dim3 grid;
-        if (blocks(I32) >= kFuseBigMinBlocks) {
+        if (c->N >= kStreamMinNodes) {
+            // Strips of 240 stored columns; segments of 64 rows, fewer while
+            // the launch has under kStreamMinBlocks workgroups.
+            const int strips = (c->nx + kStreamStore - 1) / kStreamStore;
+            int rows = 64;
+            while (rows > 8 && (long long)strips * ((c->ny + rows - 1) / rows) < kStreamMinBlocks) rows >>= 1;
+            grid = dim3(unsigned(strips), unsigned((c->ny + rows - 1) / rows), 1);
+            hipLaunchKernelGGL((k_step_ab_stream2d<S, K::force, K::comp, kNtStores>), grid, c->block, 0,
+                               c->stream, src, dst, args, rows);
+        } else if (blocks(I32) >= kFuseBigMinBlocks) {
             const FuseMap m = fuse_plan(c->nx, c->ny, I32, 0, &grid);
             hipLaunchKernelGGL((k_step_ab_fused2d<32, S, K::force, K::comp, kNtStores>), grid, c->block, 0,
                                c->stream, src, dst, args, m);
@@ -395,6 +406,7 @@ const Ops* make_ops(lbm_storage s)
     case LBM_F32: return Impl<L, float>::ops();
     case LBM_F16_DEV: return Impl<L, __half>::ops();
     case LBM_BF16_DEV: return Impl<L, __hip_bfloat16>::ops();
+    case LBM_E4M11_DEV: return Impl<L, e4m11>::ops();
     }
     return nullptr;
 }

@@ -37,6 +37,7 @@
 #include <type_traits>
 #include <utility>
 
+#include "e4m11.hpp"
 #include "lattice.hpp"
 
 namespace imexlbm {
@@ -86,6 +87,14 @@ struct Store<__hip_bfloat16> {
     static constexpr bool kDeviation = true;
     __device__ static C load(__hip_bfloat16 v) { return __bfloat162float(v); }
     __device__ static __hip_bfloat16 save(C v) { return __float2bfloat16(v); }  // nearest-even
+};
+
+template <>
+struct Store<e4m11> {
+    using C = float;
+    static constexpr bool kDeviation = true;
+    __device__ static C load(e4m11 v) { return e4m11_to_float(v); }
+    __device__ static e4m11 save(C v) { return e4m11_from_float(v); }  // nearest-even
 };
 
 // ---------------------------------------------------------------------------

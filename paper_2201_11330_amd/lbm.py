@@ -18,11 +18,11 @@ LIB_PATH = os.path.join(_PKG, "liblbm.so")
 # Enumerations of lbm.h.
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
 PERIODIC, SOLID_ENDS, WALLS_OUTSIDE, WALLS_NODAL = 0, 1, 2, 3
-F64, F32, F16_DEV, BF16_DEV = 0, 1, 2, 3
+F64, F32, F16_DEV, BF16_DEV, E4M11_DEV = 0, 1, 2, 3, 4
 FLAG_AA, FLAG_GRAPH, FLAG_COMPRESSIBLE = 1, 2, 4
 OK, EINVAL, ENOTBOUND, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 
-STORAGE_NAMES = {"f64": F64, "f32": F32, "f16": F16_DEV, "bf16": BF16_DEV}
+STORAGE_NAMES = {"f64": F64, "f32": F32, "f16": F16_DEV, "bf16": BF16_DEV, "e4m11": E4M11_DEV}
 Q_OF = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 
 # Every symbol include/lbm.h declares.
@@ -128,7 +128,7 @@ class LBM:
 
     ``tau`` is the lattice relaxation time (omega = 1/tau, nu = (tau - 1/2)/3);
     ``bc`` gives PERIODIC / SOLID_ENDS / WALLS_OUTSIDE / WALLS_NODAL per axis
-    (x, y, z); ``storage`` is "f64", "f32", "f16" or "bf16"; ``aa`` selects
+    (x, y, z); ``storage`` is "f64", "f32", "f16", "bf16" or "e4m11"; ``aa`` selects
     the in-place AA pattern; ``graph`` makes step() replay a captured HIP
     graph of 32 steps; ``compressible`` selects the equilibrium of Eq. (feq).
     Launches go to ``stream`` (default: torch's current stream at

@@ -114,7 +114,27 @@ def round_to_bf16(x):
     return np.ldexp(np.rint(np.ldexp(m, 8)), e - 8)
 
 
+E4M11_MAX = 2.0 ** -1 * (2.0 - 2.0 ** -11)  # largest finite value of the 16-bit e4m11 format
+
+
+def round_to_e4m11(x):
+    """Nearest-even rounding of FP64 values to the e4m11 storage format: 12
+    significant bits from 2^-14 up, a fixed spacing of 2^-25 below, values
+    past the largest finite (2^-1 (2 - 2^-11)) to infinity; computed with
+    frexp/ldexp."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    m, e = np.frexp(a)
+    normal = np.ldexp(np.rint(np.ldexp(m, 12)), e - 12)
+    sub = np.ldexp(np.rint(np.ldexp(a, 25)), -25)
+    q = np.where(a >= 2.0 ** -14, normal, sub)
+    q = np.where(q > E4M11_MAX, np.inf, q)
+    return np.copysign(q, x)
+
+
 def quantize(x, storage):
+    if storage == "e4m11":
+        return round_to_e4m11(x)
     if storage == "f16":
         return x.astype(np.float16).astype(np.float64)
     if storage == "bf16":
@@ -134,6 +154,9 @@ def ulp(x, storage):
     if storage == "bf16":
         m, e = np.frexp(np.maximum(a, 1e-38))
         return np.ldexp(1.0, e - 8)
+    if storage == "e4m11":
+        m, e = np.frexp(np.maximum(a, 2.0 ** -14))
+        return np.ldexp(1.0, e - 12)
     return np.spacing(a)
 
 

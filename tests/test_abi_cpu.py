@@ -35,7 +35,8 @@ def test_header_enums_match_binding():
     for name, val in [("LBM_D2Q9", lbm.D2Q9), ("LBM_D3Q19", lbm.D3Q19), ("LBM_D3Q27", lbm.D3Q27),
                       ("LBM_F64", lbm.F64),
                       ("LBM_F32", lbm.F32), ("LBM_F16_DEV", lbm.F16_DEV),
-                      ("LBM_BF16_DEV", lbm.BF16_DEV), ("LBM_PERIODIC", lbm.PERIODIC),
+                      ("LBM_BF16_DEV", lbm.BF16_DEV), ("LBM_E4M11_DEV", lbm.E4M11_DEV),
+                      ("LBM_PERIODIC", lbm.PERIODIC),
                       ("LBM_SOLID_ENDS", lbm.SOLID_ENDS), ("LBM_WALLS_OUTSIDE", lbm.WALLS_OUTSIDE),
                       ("LBM_WALLS_NODAL", lbm.WALLS_NODAL),
                       ("LBM_FLAG_AA", lbm.FLAG_AA), ("LBM_FLAG_GRAPH", lbm.FLAG_GRAPH),

@@ -160,7 +160,7 @@ def test_two_node_kernels_ab_equals_aa_bitwise_and_oracle(lattice, dims, force, 
     assert rel_err(ab.moments()[1].cpu().numpy(), u_or) <= TOL
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "e4m11"])
 @pytest.mark.parametrize("dims", [(128, 128, 1), (130, 97, 1), (7, 5, 1), (1, 1, 1), (3, 40, 1),
                                   (200, 170, 1), (3000, 200, 1), (514, 2048, 1)],
                          ids=lambda d: f"{d[0]}x{d[1]}")
@@ -188,6 +188,33 @@ def test_fused_d2q9_launches_equal_one_step_launches(storage, dims, force, comp)
         for _ in range(n):
             single.step(1)
         assert fused.steps_taken == single.steps_taken
+        assert torch.equal(fused.get_populations(), single.get_populations())
+    fused.close()
+    single.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16", "e4m11"])
+@pytest.mark.parametrize("dims", [(1000, 1100, 1), (4097, 257, 1), (256, 4096, 1), (1030, 1024, 1)],
+                         ids=lambda d: f"{d[0]}x{d[1]}")
+@pytest.mark.parametrize("force,comp", [((0, 0, 0), False), ((1e-5, -2e-5, 0), False),
+                                        ((1e-5, 0, 0), True)], ids=["plain", "force", "comp"])
+def test_streamed_d2q9_launches_equal_one_step_launches(storage, dims, force, comp):
+    """Periodic D2Q9 boxes of at least 2^20 nodes run their four-step
+    launches as strips of 240 stored columns streamed up row segments
+    (stream2d.hpp): ragged strips and segments, a strip wider than the part
+    of the box it stores (nx = 256: the second strip wraps), segments
+    shortened to 8 rows (few strips) or kept at 64 (many).  The state after
+    8, 12 and 16 steps equals that of one-step launches bit for bit."""
+    print(f"streamed D2Q9 {dims} {storage} F={force} comp={comp}", flush=True)
+    rho, u, noise = inputs(W.D2Q9, dims, "channel", seed=23, noise_amp=1e-5, bc=(0, 0, 0), U0=0.03)
+    fused = lbm.LBM(lbm.D2Q9, *dims, 0.7, force=force, storage=storage, compressible=comp)
+    single = lbm.LBM(lbm.D2Q9, *dims, 0.7, force=force, storage=storage, compressible=comp)
+    for s in (fused, single):
+        s.init_equilibrium(rho, u, noise)
+    for n in (8, 12, 16):
+        fused.step(n)
+        for _ in range(n):
+            single.step(1)
         assert torch.equal(fused.get_populations(), single.get_populations())
     fused.close()
     single.close()
@@ -278,7 +305,7 @@ def test_full_size_channel_sampled():
     assert ef <= TOL and eu <= TOL
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "e4m11"])
 @pytest.mark.parametrize("aa", [False, True], ids=["AB", "AA"])
 def test_reduced_precision_one_step(storage, aa):
     """Deviation storage: from a state exactly representable in the storage

@@ -110,7 +110,7 @@ def test_nodal_state_roundtrip_follows_eq_bb(aa):
     assert rel_err(sim.get_populations().cpu().numpy(), ref.get_populations()) <= TOL
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "e4m11"])
 @pytest.mark.parametrize("aa", [False, True], ids=["AB", "AA"])
 def test_reduced_precision_one_step(storage, aa):
     """Deviation storage with both variants on (compressible, nodal walls

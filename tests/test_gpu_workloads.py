@@ -151,13 +151,14 @@ def _rate(ts, ke, skip=100):
 
 # Measured on MI355X (this workload, these inputs): max |u - u_f64| / U0 and
 # the relative KE decay-rate error of each storage.
-MEASURED_512 = {"f32": (9.7e-6, 1.0e-3), "f16": (2.24e-3, 5.8e-2), "bf16": (2.64e-2, 0.251)}
+MEASURED_512 = {"f32": (9.7e-6, 1.0e-3), "f16": (2.24e-3, 5.8e-2), "bf16": (2.64e-2, 0.251),
+                "e4m11": (7.13e-4, 1.50e-2)}
 
 
 @pytest.mark.slow
 def test_reduced_precision_taylor_green_512():
-    """Workload D3Q19 512^3 Taylor-Green, tau = 0.6, 500 steps: FP32, FP16 and
-    BF16 storage of f - w (FP32 arithmetic) against the FP64 run on the same
+    """Workload D3Q19 512^3 Taylor-Green, tau = 0.6, 500 steps: FP32, FP16,
+    e4m11 and BF16 storage of f - w (FP32 arithmetic) against the FP64 run on the same
     inputs (population noise U(+-1e-6) from torch's device generator, seed 4,
     as in the benchmark's precision line).  Reported: max |u| error
     (absolute and / U0) and the relative error of the kinetic-energy decay
@@ -172,7 +173,7 @@ def test_reduced_precision_taylor_green_512():
               torch.from_numpy(np.array(u0, copy=True)).cuda(), noise)
     ts, ke64, u64 = _tg_run(n, "f64", steps, every, inputs)
     r64 = _rate(ts, ke64)
-    for storage in ("f32", "f16", "bf16"):
+    for storage in ("f32", "f16", "bf16", "e4m11"):
         ts, ke, u = _tg_run(n, storage, steps, every, inputs)
         du = (u - u64).abs().max().item()
         rerr = abs(_rate(ts, ke) / r64 - 1)

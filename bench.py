@@ -349,11 +349,13 @@ def run_small_2d(n=128, steps=1000, tau=0.8):
     return out
 
 
-def run_large_2d(n=4096, steps=200, warmup=40, tau=0.8):
+def run_large_2d(n=4096, steps=200, warmup=400, tau=0.8):
     """D2Q9 n^2 periodic Taylor-Green (U0 = 0.01), FP64 AB: a box far larger
     than the caches, where the four-step launches (strips streamed up the
     rows) read and write the state once per four steps (36 B per update)
-    against the 144 B a one-step pass moves."""
+    against the 144 B a one-step pass moves.  400 untimed steps: after the
+    host-side set-up leaves the GPU idle, these launches take ~50 of them
+    (~30 ms) to reach their steady duration (670 -> 487 us)."""
     import torch
 
     from paper_2201_11330_amd import lbm
@@ -375,7 +377,7 @@ def run_large_2d(n=4096, steps=200, warmup=40, tau=0.8):
     mlups = n * n * steps / (ms * 1e-3) / 1e6
     one_step_bound = HBM_PEAK_GBS * 1e3 / 144.0
     return {"workload": f"D2Q9 {n}^2 periodic Taylor-Green, tau={tau}, {steps} steps, FP64 AB",
-            "kernel": "k_step_ab_stream2d (4 steps per launch, strips of 240 columns streamed "
+            "kernel": "k_step_ab_stream2d (4 steps per launch, strips of 224 columns streamed "
                       "up row segments)",
             "mlups": round(mlups, 1), "bytes_per_update_moved": 36,
             "one_step_hbm_bound_mlups": round(one_step_bound, 1),

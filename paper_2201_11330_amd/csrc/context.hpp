@@ -83,6 +83,9 @@ struct lbm_ctx {
     int pairs_shift = 7;
     dim3 pairs_grid;
 
+    // Rows per segment of the streamed D2Q9 launches (0: not planned yet).
+    int stream_rows = 0;
+
     // LBM_FLAG_GRAPH: kGraphSteps steps captured once, replayed by lbm_step.
     bool use_graph = false;
     hipStream_t capture_stream = nullptr;

@@ -140,14 +140,23 @@ struct Impl {
         const auto args = step_args<typename Store<S>::C>(c);
         dim3 grid;
         if (c->N >= kStreamMinNodes) {
-            // Strips of 240 stored columns; segments of 64 rows, fewer while
-            // the launch has under kStreamMinBlocks workgroups.
-            const int strips = (c->nx + kStreamStore - 1) / kStreamStore;
-            int rows = 64;
-            while (rows > 8 && (long long)strips * ((c->ny + rows - 1) / rows) < kStreamMinBlocks) rows >>= 1;
-            grid = dim3(unsigned(strips), unsigned((c->ny + rows - 1) / rows), 1);
-            hipLaunchKernelGGL((k_step_ab_stream2d<S, K::force, K::comp, kNtStores>), grid, c->block, 0,
-                               c->stream, src, dst, args, rows);
+            // Strips of kStreamStore stored columns, segments of rows chosen
+            // once per context from the kernel's occupancy (stream_rows).
+            const auto kernel = k_step_ab_stream2d<S, K::force, K::comp, kNtStores>;
+            if (c->stream_rows == 0) {
+                int per_cu = 0, cus = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+                    per_cu < 1 || cus < 1) {
+                    (void)hipGetLastError();
+                    per_cu = 4;  // unknown: assume a GPU of 256 CUs, 4 workgroups each
+                    cus = 256;
+                }
+                c->stream_rows = stream_rows(c->nx, c->ny, (long long)per_cu * cus);
+            }
+            const int rows = c->stream_rows;
+            grid = dim3(unsigned((c->nx + kStreamStore - 1) / kStreamStore), unsigned((c->ny + rows - 1) / rows), 1);
+            hipLaunchKernelGGL(kernel, grid, c->block, 0, c->stream, src, dst, args, rows);
         } else if (blocks(I32) >= kFuseBigMinBlocks) {
             const FuseMap m = fuse_plan(c->nx, c->ny, I32, 0, &grid);
             hipLaunchKernelGGL((k_step_ab_fused2d<32, S, K::force, K::comp, kNtStores>), grid, c->block, 0,

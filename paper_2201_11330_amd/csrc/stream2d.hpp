@@ -2,7 +2,7 @@
 // (two-lattice pattern), streaming up the rows of a strip of columns.
 //
 // A 256-item workgroup owns a strip of 256 columns (one per work-item: the
-// kStreamStore = 240 columns it stores and 8 more on each side) and a
+// kStreamStore = 224 columns it stores and 16 more on each side) and a
 // segment of rows.  It walks up the rows once: in iteration j it loads
 // stored row j (the post-collision state of the previous launch, "level
 // 0"), and each level k = 1..4 pulls (Eq. (propagation)) and collides (Eq.
@@ -14,15 +14,16 @@
 // (propagation) in x: a wave shift between lanes, and between the
 // wavefronts of the workgroup through LDS, one barrier per level and row).
 // Level 4's rows are stored.  The two outermost columns lose one valid
-// column per level, so the 8 columns on each side cover the 4 levels, and
-// the 240 stored columns (15 lines of 128 bytes) start on a line.  A
+// column per level, so 4 columns on each side would cover the 4 levels;
+// with 16 the strip starts on a 128-byte line and each wavefront stores
+// whole lines (with 8, whose 240 stored columns also start on a line, the
+// wavefronts split lines between them: 4096^2 FP64 ran 2 % slower).  A
 // segment re-reads 4 rows below and above its stored rows.
 //
 // Against the regions of fused2d.hpp (32 x 32 nodes around 24 x 24 stored
-// ones), a launch fetches the state 1.13 x (256 of 240 columns over 17
-// lines per 15 stored) x (rows + 8) / rows instead of ~2.7 x, writes whole
-// lines, and repeats (256 / 240) (rows + 8) / rows of the collisions
-// instead of 1.78 x.  The arithmetic per node and step is that of the
+// ones), a launch fetches the state 1.14 x (256 of 224 columns) x
+// (rows + 8) / rows instead of ~2.7 x, writes whole lines, and repeats
+// that fraction of the collisions instead of 1.78 x.  The arithmetic per node and step is that of the
 // one-step kernels, in the same order, so the state after 4 steps is bit
 // for bit that of 4 one-step launches (each level rounds through the
 // storage type, as a store and reload would).
@@ -33,14 +34,37 @@
 namespace imexlbm {
 
 constexpr int kStreamCols = 256;  // columns per workgroup, one per work-item
-constexpr int kStreamHalo = 8;    // loaded columns on each side of the stored ones
-constexpr int kStreamStore = kStreamCols - 2 * kStreamHalo;  // 240 stored columns
+constexpr int kStreamHalo = 16;   // loaded columns on each side of the stored ones
+constexpr int kStreamStore = kStreamCols - 2 * kStreamHalo;  // 224 stored columns
 constexpr int kStreamLevels = 4;  // steps per launch
 // Boxes of at least kStreamMinNodes nodes take these launches (smaller ones
-// the regions of fused2d.hpp); the row segments shrink from 64 rows down to
-// 8 while a launch has fewer than kStreamMinBlocks workgroups.
+// the regions of fused2d.hpp).
 constexpr unsigned kStreamMinNodes = 1u << 20;
-constexpr long long kStreamMinBlocks = 1024;
+
+// Rows per segment for an nx x ny box when the GPU runs `slots` workgroups
+// of the kernel at once.  Every workgroup runs rows + 2 H iterations, so a
+// launch takes about ceil(workgroups / slots) rounds of that many: the rows
+// from 8 to 256 that minimise the product (the fewest among equals).  Long
+// segments re-read fewer rows (8 per segment) but leave part of the last
+// round idle unless the workgroups fill it.  Measured at 4096^2 FP64 (19
+// strips, 768 slots): 103 rows (760 workgroups, the rule's choice) 135,500-
+// 136,700 MLUPS; 64 rows (1216) 130,400-132,300; 52 (1501) 131,900; 86
+// (912) 121,400; 120 (665) 128,500.
+inline int stream_rows(int nx, int ny, long long slots)
+{
+    const long long strips = (nx + kStreamStore - 1) / kStreamStore;
+    int best = 8;
+    long long best_cost = -1;
+    for (int rows = 8; rows <= 256; ++rows) {
+        const long long wg = strips * ((ny + rows - 1) / rows);
+        const long long cost = (wg + slots - 1) / slots * (rows + 2 * kStreamLevels);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = rows;
+        }
+    }
+    return best;
+}
 
 // Lane i receives v of lane i - 1 (SHIFT = 0x138, wave_shr:1) or of lane
 // i + 1 (SHIFT = 0x130, wave_shl:1); the edge lane keeps its own v.

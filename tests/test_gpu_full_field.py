@@ -102,11 +102,11 @@ def test_taylor_green_2d_128_1000_steps_one_call():
     assert abs(red["ke"] / red_or["ke"] - 1) <= 1e-10
 
 
-def test_d2q9_4096_four_step_regions_whole_field():
+def test_d2q9_4096_four_step_launches_whole_field():
     """D2Q9 4096^2 periodic Taylor-Green, tau = 0.8, 8 steps in one call: two
-    launches of the four-step kernel on 32 x 32-node regions (four nodes per
-    work-item, the benchmark's large_2d launch), whole field against the
-    oracle."""
+    four-step launches streamed up strips of 224 columns (the benchmark's
+    large_2d launch, segments of 103 rows with a ragged last one), whole
+    field against the oracle."""
     n, tau, steps = 4096, 0.8, 8
     rho, u = W.taylor_green_2d(n, U0=0.01)
     noise = W.population_noise(W.D2Q9, (n, n, 1), 1e-6, seed=40)
@@ -116,7 +116,7 @@ def test_d2q9_4096_four_step_regions_whole_field():
     ref = oracle.Sim(oracle.D2Q9, n, n, 1, tau=tau)
     ref.init_equilibrium(rho, u, noise)
     ref.step(steps)
-    ef, eu = _compare("D2Q9 4096^2 x 8 (32x32 regions)", sim, ref)
+    ef, eu = _compare("D2Q9 4096^2 x 8 (streamed strips)", sim, ref)
     sim.close()
     ref.close()
     assert ef <= TOL and eu <= TOL

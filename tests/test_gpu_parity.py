@@ -200,10 +200,10 @@ def test_fused_d2q9_launches_equal_one_step_launches(storage, dims, force, comp)
                                         ((1e-5, 0, 0), True)], ids=["plain", "force", "comp"])
 def test_streamed_d2q9_launches_equal_one_step_launches(storage, dims, force, comp):
     """Periodic D2Q9 boxes of at least 2^20 nodes run their four-step
-    launches as strips of 240 stored columns streamed up row segments
+    launches as strips of 224 stored columns streamed up row segments
     (stream2d.hpp): ragged strips and segments, a strip wider than the part
-    of the box it stores (nx = 256: the second strip wraps), segments
-    shortened to 8 rows (few strips) or kept at 64 (many).  The state after
+    of the box it stores (nx = 256: the second strip wraps), and segment
+    lengths the launch plan picks for each box.  The state after
     8, 12 and 16 steps equals that of one-step launches bit for bit."""
     print(f"streamed D2Q9 {dims} {storage} F={force} comp={comp}", flush=True)
     rho, u, noise = inputs(W.D2Q9, dims, "channel", seed=23, noise_amp=1e-5, bc=(0, 0, 0), U0=0.03)

@@ -538,12 +538,14 @@ def host_cpu_model():
 
 def line_fp16(args, mlups):
     """FP16 storage (f - w) of the main workload.  Its launches are short
-    (~205 us): 300 untimed steps (~60 ms) let the clocks settle first."""
+    (~205 us): at least 500 untimed steps (~100 ms) let the clocks settle
+    first, and at least 500 timed steps average out their spread."""
     n = args.n
-    r = run_gpu(n, "f16", args.pattern, args.steps, max(args.warmup, 300))
-    m = n ** 3 * args.steps / (r["total_ms"] * 1e-3) / 1e6
+    steps, warmup = max(args.steps, 500), max(args.warmup, 500)
+    r = run_gpu(n, "f16", args.pattern, steps, warmup)
+    m = n ** 3 * steps / (r["total_ms"] * 1e-3) / 1e6
     a = 2 * 19 * 2 * n ** 3 / (r["launch_ms_mean"] * 1e-3) / 1e9
-    return {"kernel": step_kernel_name(n, "f16", args.pattern), "warmup": max(args.warmup, 300),
+    return {"kernel": step_kernel_name(n, "f16", args.pattern), "steps": steps, "warmup": warmup,
             "mlups": round(m, 1), "speedup_vs_f64": round(m / mlups, 3) if mlups else None,
             "launch_ms_mean": round(r["launch_ms_mean"], 5), "achieved_gbs": round(a, 1),
             "frac": round(a / HBM_PEAK_GBS, 4)}

@@ -41,49 +41,43 @@ __host__ __device__ inline float e4m11_bits_f32(uint32_t u)
     return v;
 }
 
-// FP32 -> e4m11, round to nearest, ties to even.  The normal, subnormal and
-// non-finite results are all computed and one is selected by masks, with no
-// branches (a conditional expression here was compiled into branches that
-// serialised the loads of a kernel).
+// FP32 -> e4m11, round to nearest, ties to even, without branches (a
+// conditional expression here was compiled into branches that serialised
+// the loads of a kernel), in about 14 instructions.
 __host__ __device__ inline e4m11 e4m11_from_float(float v)
 {
     const uint32_t u = e4m11_f32_bits(v);
-    const uint32_t sign = (u >> 16) & 0x8000u;
     const uint32_t a = u & 0x7FFFFFFFu;
-    // Normal (|v| >= 2^-14, FP32 biased exponent e32 >= 113): the FP32
-    // exponent 127 + k becomes field 15 + k; 12 fraction bits are dropped
-    // with round-to-nearest-even, a carry out of the fraction moves into the
-    // exponent, and past field 14 the result is infinity.
-    uint32_t rn = (a - (112u << 23) + 0x7FFu + ((a >> 12) & 1u)) >> 12;
-    rn = rn > 0x7800u ? 0x7800u : rn;
-    // Subnormal (|v| < 2^-14): M = |v| 2^25 rounded to the nearest integer,
-    // ties to even (the FP32 product is exact, and rintf rounds to nearest
-    // even); M = 2^11 is the smallest normal (field 1, fraction 0).  The
-    // clamp keeps the product finite and small for the other inputs.
-    const float av = e4m11_bits_f32(a);
-    const uint32_t rs = uint32_t(__builtin_rintf((av < 0x1p-14f ? av : 0x1p-14f) * 0x1p25f));
-    // Infinity, or NaN with a nonzero fraction.
-    const uint32_t rx = 0x7800u | (uint32_t(a > 0x7F800000u) << 10);
-    const uint32_t use_n = 0u - uint32_t(a >= (113u << 23));
-    const uint32_t use_x = 0u - uint32_t(a >= 0x7F800000u);
-    uint32_t r = rs ^ ((rs ^ rn) & use_n);
-    r = r ^ ((r ^ rx) & use_x);
-    return {uint16_t(sign | r)};
+    // Normal result (|v| >= 2^-14): the FP32 exponent 127 + k becomes field
+    // 15 + k, and 12 fraction bits are dropped with round-to-nearest-even; a
+    // carry out of the fraction moves into the exponent.  Below 2^-14 this
+    // is negative.
+    const int32_t rn = int32_t(a + 0x7FFu + ((a >> 12) & 1u) - (112u << 23)) >> 12;
+    // Subnormal result: M = |v| 2^25 rounded to the nearest integer, ties to
+    // even, by one fused multiply-add with 2^23 (the product is exact and the
+    // sum rounds at units); |v| is capped at 2^-14, where M = 2^11 is the
+    // code of 2^-14 itself, so for normal inputs rs <= rn.
+    const float cap = e4m11_bits_f32(a) < 0x1p-14f ? e4m11_bits_f32(a) : 0x1p-14f;
+    const int32_t rs = int32_t(e4m11_f32_bits(__builtin_fmaf(cap, 0x1p25f, 0x1p23f)) - 0x4B000000u);
+    uint32_t r = uint32_t(rn > rs ? rn : rs);
+    // Past the largest finite value (and for infinities): infinity; NaN
+    // keeps a nonzero fraction.
+    r = r < 0x7800u ? r : 0x7800u;
+    r |= uint32_t(a > 0x7F800000u) << 10;
+    return {uint16_t(((u >> 16) & 0x8000u) | r)};
 }
 
-// e4m11 -> FP32, exact.  With the 15 low bits shifted into an FP32's
-// exponent and fraction (E << 23 | M << 12), that FP32 is 2^(E-127)
-// (1 + M/2^11) for E >= 1 and the denormal M 2^-137 for E = 0, so a product
-// with 2^112 gives 2^(E-15) (1 + M/2^11) and M 2^-25 exactly (the kernels
-// keep FP32 denormals); E = 15 is selected as infinity or NaN.
+// e4m11 -> FP32, exact.  The 15 low bits shifted into an FP32's exponent and
+// fraction (E << 23 | M << 12), with the sign in place, make the FP32
+// 2^(E-127) (1 + M/2^11) for E >= 1 and the denormal M 2^-137 for E = 0, so a
+// product with 2^112 gives 2^(E-15) (1 + M/2^11) and M 2^-25 exactly (the
+// kernels keep FP32 denormals); E = 15 becomes infinity or NaN.
 __host__ __device__ inline float e4m11_to_float(e4m11 h)
 {
-    const uint32_t sign = uint32_t(h.bits & 0x8000u) << 16;
-    const uint32_t em = uint32_t(h.bits & 0x7FFFu) << 12;
-    uint32_t r = e4m11_f32_bits(e4m11_bits_f32(em) * 0x1p112f);
-    const uint32_t use_x = 0u - uint32_t(em >= (15u << 23));
-    r = r ^ ((r ^ (0x7F800000u | (em & 0x7FFFFFu))) & use_x);
-    return e4m11_bits_f32(sign | r);
+    const uint32_t em = uint32_t(h.bits & 0x7FFFu);
+    const uint32_t x = ((uint32_t(h.bits) & 0x8000u) << 16) | (em << 12);
+    const float mag = e4m11_bits_f32(x) * 0x1p112f;
+    return em >= 0x7800u ? e4m11_bits_f32(x | 0x7F800000u) : mag;
 }
 
 }  // namespace imexlbm

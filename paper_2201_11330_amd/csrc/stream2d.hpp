@@ -23,10 +23,10 @@
 // Against the regions of fused2d.hpp (32 x 32 nodes around 24 x 24 stored
 // ones), a launch fetches the state 1.14 x (256 of 224 columns) x
 // (rows + 8) / rows instead of ~2.7 x, writes whole lines, and repeats
-// that fraction of the collisions instead of 1.78 x.  The arithmetic per node and step is that of the
-// one-step kernels, in the same order, so the state after 4 steps is bit
-// for bit that of 4 one-step launches (each level rounds through the
-// storage type, as a store and reload would).
+// that fraction of the collisions instead of 1.78 x.  The arithmetic per
+// node and step is that of the one-step kernels, in the same order, so the
+// state after 4 steps is bit for bit that of 4 one-step launches (each
+// level rounds through the storage type, as a store and reload would).
 #pragma once
 
 #include "kernels.hpp"

@@ -440,10 +440,13 @@ def run_adjoint(n=128, steps=500, k=50, storage="f32", tau=0.7):
 def step_kernel_name(n, storage, pattern):
     """The step kernel liblbm launches for this workload: periodic FP64
     boxes with an even nx and at least 2^20 nodes run two nodes per
-    work-item (k_step_ab_pairs, or k_step_aa_even/odd_pairs), everything
-    else one node."""
+    work-item (k_step_ab_pairs, or k_step_aa_even/odd_pairs); FP32 and e4m11
+    two-lattice steps of a box whose nx is a power of two from 64 to 4096
+    take the row-addressed kernel; everything else one node."""
     if storage == "f64" and n % 2 == 0 and n ** 3 >= 1 << 20:
         return f"k_step_{pattern}_pairs<D3Q19,f64>"
+    if storage in ("f32", "e4m11") and pattern == "ab" and 64 <= n <= 4096 and n & (n - 1) == 0:
+        return f"k_step_ab_rows<D3Q19,{storage}>"
     return f"k_step_{pattern}<D3Q19,{storage}>"
 
 

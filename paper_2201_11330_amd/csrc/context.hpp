@@ -82,6 +82,10 @@ struct lbm_ctx {
     bool pairs = false;
     int pairs_shift = 7;
     dim3 pairs_grid;
+    // Rows lie inside one tile and wavefronts inside one row (nx a power of
+    // two, 64 <= nx <= tile length): the one-node AB step of a box without
+    // walls may take k_step_ab_rows (FP32 and e4m11 storage).
+    bool rows = false;
 
     // Rows per segment of the streamed D2Q9 launches (0: not planned yet).
     int stream_rows = 0;

@@ -48,6 +48,16 @@ struct Impl {
                 return;
             }
         }
+        // Row addressing where it measured faster (D3Q19 256^3 and 512^3):
+        // e4m11 storage +23 % (its step is bound by the conversion
+        // arithmetic), FP32 +0.5 %; FP16 and BF16 ran 2-6 % slower with it.
+        if constexpr (!K::walls && (std::is_same_v<S, e4m11> || std::is_same_v<S, float>)) {
+            if (c->rows) {
+                hipLaunchKernelGGL((k_step_ab_rows<L, S, K::force, K::comp, kNtStores>), c->grid, c->block, 0,
+                                   c->stream, src, dst, step_args<typename Store<S>::C>(c));
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_step_ab<L, S, K::walls, K::force, K::comp, kNtStores>), c->grid, c->block, 0,
                            c->stream, src, dst, step_args<typename Store<S>::C>(c));
     }

@@ -69,6 +69,7 @@ void plan_launch(lbm_ctx* c)
     // wider accesses gain (measured 2-4 % slower).
     c->pairs = c->storage == LBM_F64 && c->lattice != LBM_D3Q27 && c->nx % 2 == 0 &&
                c->N >= (1u << 20);
+    c->rows = c->nx >= 64 && (c->nx & (c->nx - 1)) == 0 && c->nx <= (1 << c->S);
     if (c->pairs) {
         const int half = c->nx / 2;
         int lanes = 1, s2 = 0;

@@ -160,6 +160,58 @@ def test_two_node_kernels_ab_equals_aa_bitwise_and_oracle(lattice, dims, force, 
     assert rel_err(ab.moments()[1].cpu().numpy(), u_or) <= TOL
 
 
+@pytest.mark.parametrize("storage", ["f32", "e4m11"])
+@pytest.mark.parametrize("lattice,dims", [
+    (W.D2Q9, (64, 50, 1)), (W.D3Q19, (64, 24, 10)), (W.D3Q19, (256, 5, 3)), (W.D3Q27, (128, 9, 7)),
+], ids=lambda v: str(v))
+@pytest.mark.parametrize("force,comp", [((0, 0, 0), False), ((1e-5, -2e-5, 0), False),
+                                        ((1e-5, 0, 0), True)], ids=["plain", "force", "comp"])
+def test_row_addressed_steps_equal_per_node_steps_and_oracle(storage, lattice, dims, force, comp):
+    """Periodic boxes with nx a power of two (64 to the tile length) in FP32
+    or e4m11 storage step one node per work-item with the addresses of the
+    source rows computed once per wavefront (rows of one and of several
+    wavefronts, D2Q9, D3Q19, D3Q27).  The AA pattern and an all-fluid solid
+    mask take the per-node kernels, which apply the same collision to the
+    same populations: all three agree bit for bit after 1, 2, 3 and 6 steps.
+    From a state exactly representable in the storage format, the first step
+    is the FP64 oracle's step rounded to the format, within one unit in the
+    last place plus FP32 arithmetic error."""
+    import oracle
+    print(f"row-addressed {lattice} {dims} {storage} F={force} comp={comp}", flush=True)
+    rho, u, noise = inputs(lattice, dims, "channel", seed=31, noise_amp=1e-4, bc=(0, 0, 0), U0=0.04)
+    ref = oracle.Sim(lattice, *dims, tau=0.7, force=force, compressible=comp)
+    ref.init_equilibrium(rho, u, noise)
+    _, t = oracle.lattice_tables(lattice)
+    tw = t[:, None, None, None] * np.ones((1,) + rho.shape)
+    g0 = quantize(ref.get_populations() - tw, storage)
+    g0[np.abs(g0) < 1e-8] = 0.0
+    f0 = g0 + tw
+    ref.set_populations(f0)
+    sims = [lbm.LBM(lattice, *dims, 0.7, force=force, storage=storage, compressible=comp, aa=aa)
+            for aa in (False, True, False)]
+    sims[2].set_solid(np.zeros(dims[::-1], dtype=np.uint8))
+    for s in sims:
+        s.set_populations(f0)
+    ref.step(1)
+    g_ref = ref.get_populations() - tw
+    ref.close()
+    for k, n in enumerate((1, 1, 1, 3)):
+        for s in sims:
+            for _ in range(n):  # one step per launch (D2Q9 would fuse lbm_step(n >= 4))
+                s.step(1)
+        f = sims[0].get_populations()
+        assert torch.equal(f, sims[1].get_populations())
+        assert torch.equal(f, sims[2].get_populations())
+        if k == 0:
+            g = f.cpu().numpy() - tw
+            tol = ulp(g_ref, storage) + 64 * np.finfo(np.float32).eps * np.abs(g_ref).max()
+            worst = (np.abs(g - g_ref) / tol).max()
+            print(f"  first step: worst error / tolerance = {worst:.3f}", flush=True)
+            assert worst <= 1.0
+    for s in sims:
+        s.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "e4m11"])
 @pytest.mark.parametrize("dims", [(128, 128, 1), (130, 97, 1), (7, 5, 1), (1, 1, 1), (3, 40, 1),
                                   (200, 170, 1), (3000, 200, 1), (514, 2048, 1)],

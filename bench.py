@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the extra lines (FP16 storage, compressible model, the other "
-                         "pattern, adjoint, channels, sphere box, D2Q9 boxes)")
+                         "pattern, 2000-step run, precision, adjoint, channels, sphere box, D2Q9 "
+                         "boxes)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-probe", action="store_true",
@@ -201,6 +202,49 @@ def run_channel_sustained(steps=20000, chunk=1000, warmup=10, nx=512, ny=128, nz
             "mlups": round(mlups, 1),
             "achieved_gbs": round(304 * nodes * chunk * nchunks / (total * 1e-3) / 1e9, 1),
             "frac": round(304 * nodes * chunk * nchunks / (total * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "us_per_step": round(total * 1e3 / (chunk * nchunks), 2),
+            "chunk_mlups_first_last": [round(per[0], 1), round(per[-1], 1)],
+            "chunk_mlups_min_max": [round(min(per), 1), round(max(per), 1)],
+            "wall_s": round(wall, 3)}
+
+
+def run_taylor_green_sustained(n=256, steps=2000, chunk=250, warmup=100, tau=0.6):
+    """The headline workload (D3Q19 n^3 periodic FP64 Taylor-Green with
+    1e-6 noise, seed 2) for `steps` steps issued as lbm_step(chunk) calls,
+    an event on the launch stream after each: the sustained rate of the
+    benchmark's step kernel and how it changes over the run."""
+    import torch
+
+    from paper_2201_11330_amd import lbm
+    from paper_2201_11330_amd import workloads as W
+
+    rho, u = W.taylor_green_3d(n, U0=0.05)
+    noise = W.population_noise(W.D3Q19, (n, n, n), 1e-6, seed=2)
+    sim = lbm.LBM(lbm.D3Q19, n, n, n, tau)
+    sim.init_equilibrium(rho, u, noise)
+    del rho, u, noise
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    nchunks = steps // chunk
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nchunks + 1)]
+    wall0 = time.perf_counter()
+    ev[0].record(sim.stream)
+    for i in range(nchunks):
+        sim.step(chunk)
+        ev[i + 1].record(sim.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    sim.close()
+    nodes = n ** 3
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(nchunks)]
+    per = [nodes * chunk / (m * 1e-3) / 1e6 for m in ms]
+    total = sum(ms)
+    gbs = 304 * nodes * chunk * nchunks / (total * 1e-3) / 1e9
+    return {"workload": f"D3Q19 {n}^3 periodic FP64 Taylor-Green, tau={tau}, {chunk * nchunks} steps "
+                        f"({nchunks} x lbm_step({chunk})) after {warmup} untimed",
+            "kernel": step_kernel_name(n, "f64", "ab"),
+            "mlups": round(nodes * chunk * nchunks / (total * 1e-3) / 1e6, 1),
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
             "us_per_step": round(total * 1e3 / (chunk * nchunks), 2),
             "chunk_mlups_first_last": [round(per[0], 1), round(per[-1], 1)],
             "chunk_mlups_min_max": [round(min(per), 1), round(max(per), 1)],
@@ -582,6 +626,7 @@ EXTRA_LINES = {
     "fp16_store": line_fp16,
     "compressible": line_compressible,
     "aa_pattern": line_other_pattern,
+    "sustained_256": lambda args, mlups: run_taylor_green_sustained(),
     "precision_512": lambda args, mlups: run_precision(),
     "adjoint": lambda args, mlups: run_adjoint(),
     "channel": lambda args, mlups: run_channel(),

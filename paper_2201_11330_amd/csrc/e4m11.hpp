@@ -43,27 +43,29 @@ __host__ __device__ inline float e4m11_bits_f32(uint32_t u)
 
 // FP32 -> e4m11, round to nearest, ties to even, without branches (a
 // conditional expression here was compiled into branches that serialised
-// the loads of a kernel), in about 14 instructions.
+// the loads of a kernel), in about 12 instructions.
 __host__ __device__ inline e4m11 e4m11_from_float(float v)
 {
     const uint32_t u = e4m11_f32_bits(v);
-    const uint32_t a = u & 0x7FFFFFFFu;
-    // Normal result (|v| >= 2^-14): the FP32 exponent 127 + k becomes field
-    // 15 + k, and 12 fraction bits are dropped with round-to-nearest-even; a
-    // carry out of the fraction moves into the exponent.  Below 2^-14 this
-    // is negative.
-    const int32_t rn = int32_t(a + 0x7FFu + ((a >> 12) & 1u) - (112u << 23)) >> 12;
-    // Subnormal result: M = |v| 2^25 rounded to the nearest integer, ties to
-    // even, by one fused multiply-add with 2^23 (the product is exact and the
-    // sum rounds at units); |v| is capped at 2^-14, where M = 2^11 is the
-    // code of 2^-14 itself, so for normal inputs rs <= rn.
-    const float cap = e4m11_bits_f32(a) < 0x1p-14f ? e4m11_bits_f32(a) : 0x1p-14f;
-    const int32_t rs = int32_t(e4m11_f32_bits(__builtin_fmaf(cap, 0x1p25f, 0x1p23f)) - 0x4B000000u);
-    uint32_t r = uint32_t(rn > rs ? rn : rs);
-    // Past the largest finite value (and for infinities): infinity; NaN
+    // For |v| in [2^e, 2^(e+1)) let c = 2^(max(e, -14) + 12).  The sum |v| + c
+    // lies in [c, 2c), where FP32's spacing is 2^(max(e, -14) - 11), the
+    // spacing of the format at |v| (normal and subnormal alike); so the sum
+    // rounds |v| to the format, to nearest with ties to even (c is a multiple
+    // of twice that spacing), and subtracting c again is exact.  From
+    // |v| >= 2^116 on c is the tiny negative FP32 0x8...; the sum leaves |v|
+    // unchanged, and so do infinity and NaN.
+    uint32_t ce = u & 0x7F800000u;
+    ce = ce > 0x38800000u ? ce : 0x38800000u;  // 2^max(e, -14)
+    const float c = e4m11_bits_f32(ce + (12u << 23));
+    const float q = (__builtin_fabsf(v) + c) - c;
+    // q 2^-112 has the FP32 exponent field E and fraction M << 12 for a
+    // normal result, and is the FP32 denormal M 2^-137 for a subnormal one
+    // (exact either way): its bits shifted right by 12 are the code.  Past
+    // the largest finite value (and for infinity): the code of infinity; NaN
     // keeps a nonzero fraction.
+    uint32_t r = e4m11_f32_bits(q * 0x1p-112f) >> 12;
     r = r < 0x7800u ? r : 0x7800u;
-    r |= uint32_t(a > 0x7F800000u) << 10;
+    r |= v != v ? 0x400u : 0u;
     return {uint16_t(((u >> 16) & 0x8000u) | r)};
 }
 
@@ -71,13 +73,16 @@ __host__ __device__ inline e4m11 e4m11_from_float(float v)
 // fraction (E << 23 | M << 12), with the sign in place, make the FP32
 // 2^(E-127) (1 + M/2^11) for E >= 1 and the denormal M 2^-137 for E = 0, so a
 // product with 2^112 gives 2^(E-15) (1 + M/2^11) and M 2^-25 exactly (the
-// kernels keep FP32 denormals); E = 15 becomes infinity or NaN.
+// kernels keep FP32 denormals); E = 15, the only codes whose product reaches
+// 1, becomes infinity or NaN.
 __host__ __device__ inline float e4m11_to_float(e4m11 h)
 {
-    const uint32_t em = uint32_t(h.bits & 0x7FFFu);
-    const uint32_t x = ((uint32_t(h.bits) & 0x8000u) << 16) | (em << 12);
+    // The code sign-extended and shifted left by 12 holds E and M in bits
+    // 26..12 and the sign in bits 31..27; clearing bits 30..27 leaves
+    // sign | E << 23 | M << 12.
+    const uint32_t x = (uint32_t(int32_t(int16_t(h.bits))) << 12) & 0x87FFF000u;
     const float mag = e4m11_bits_f32(x) * 0x1p112f;
-    return em >= 0x7800u ? e4m11_bits_f32(x | 0x7F800000u) : mag;
+    return __builtin_fabsf(mag) >= 1.0f ? e4m11_bits_f32(x | 0x7F800000u) : mag;
 }
 
 }  // namespace imexlbm

@@ -2,8 +2,9 @@
 compiled here as host code by a small harness) against an independent
 numpy restatement of the format: every code decodes to the value its bit
 fields define, and FP32 values -- every power-of-two boundary, the ties
-halfway between neighbouring codes, the subnormal range, the overflow
-threshold, NaN and infinities, and random values over the whole range --
+halfway between neighbouring codes, the subnormal range, FP32 denormals, the
+overflow threshold, the largest FP32 values, NaN and infinities, and random
+values over the whole range --
 encode to the nearest code with ties to even."""
 import os
 import subprocess
@@ -68,7 +69,11 @@ def test_encode_rounds_to_nearest_even(harness, tmp_path):
           rng.uniform(0, 1, 200000), 10.0 ** rng.uniform(-12, 0, 200000),
           [2.0 ** -26, 2.0 ** -26 * (1 + 2 ** -23), 2.0 ** -27, 1e-30, 0.0,
            E4M11_MAX, (E4M11_MAX + 1.0) / 2, np.nextafter(np.float32((E4M11_MAX + 1.0) / 2), 0),
-           1.0, 3.5, 1e30]]
+           1.0, 3.5, 1e30,
+           # FP32 denormals, and magnitudes around 2^116, where the rounding
+           # constant of the encoder leaves the FP32 range
+           1e-40, 2.0 ** -149, 2.0 ** -126, 2.0 ** 115, 2.0 ** 116, 2.0 ** 120,
+           float(np.finfo(np.float32).max)]]
     x = np.concatenate([np.asarray(a, dtype=np.float64) for a in xs]).astype(np.float32)
     x = np.concatenate([x, -x])
     assert np.all(np.isfinite(x))

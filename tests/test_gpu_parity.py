@@ -160,6 +160,70 @@ def test_two_node_kernels_ab_equals_aa_bitwise_and_oracle(lattice, dims, force, 
     assert rel_err(ab.moments()[1].cpu().numpy(), u_or) <= TOL
 
 
+def _narrow_storage_kernels_agree(storage, lattice, dims, force, comp, counts):
+    """The two-lattice step of a periodic box in `storage` (f - w), the AA
+    pattern and an all-fluid solid mask (per-node kernels) from one state
+    exactly representable in the storage: bit for bit after every count of
+    one-step launches, and the first step within one storage ulp + FP32
+    arithmetic of the FP64 oracle's step."""
+    import oracle
+    rho, u, noise = inputs(lattice, dims, "channel", seed=31, noise_amp=1e-4, bc=(0, 0, 0), U0=0.04)
+    ref = oracle.Sim(lattice, *dims, tau=0.7, force=force, compressible=comp)
+    ref.init_equilibrium(rho, u, noise)
+    del rho, u, noise
+    _, t = oracle.lattice_tables(lattice)
+    tw = t[:, None, None, None] * np.ones((1,) + tuple(dims[::-1]))
+    g0 = quantize(ref.get_populations() - tw, storage)
+    g0[np.abs(g0) < 1e-8] = 0.0
+    f0 = g0 + tw
+    del g0
+    ref.set_populations(f0)
+    sims = [lbm.LBM(lattice, *dims, 0.7, force=force, storage=storage, compressible=comp, aa=aa)
+            for aa in (False, True, False)]
+    sims[2].set_solid(np.zeros(dims[::-1], dtype=np.uint8))
+    for s in sims:
+        s.set_populations(f0)
+    del f0
+    ref.step(1)
+    g_ref = ref.get_populations() - tw
+    ref.close()
+    for k, n in enumerate(counts):
+        for s in sims:
+            for _ in range(n):  # one step per launch (D2Q9 would fuse lbm_step(n >= 4))
+                s.step(1)
+        f = sims[0].get_populations()
+        assert torch.equal(f, sims[1].get_populations())
+        assert torch.equal(f, sims[2].get_populations())
+        if k == 0:
+            g = f.cpu().numpy() - tw
+            tol = ulp(g_ref, storage) + 64 * np.finfo(np.float32).eps * np.abs(g_ref).max()
+            worst = (np.abs(g - g_ref) / tol).max()
+            print(f"  first step: worst error / tolerance = {worst:.3f}", flush=True)
+            assert worst <= 1.0
+        del f
+    for s in sims:
+        s.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "e4m11"])
+@pytest.mark.parametrize("lattice,dims", [
+    (W.D3Q19, (2, 1024, 512)), (W.D3Q19, (34, 200, 155)), (W.D3Q19, (128, 96, 86)),
+    (W.D3Q19, (1030, 33, 31)), (W.D2Q9, (18, 58255, 1)), (W.D2Q9, (514, 2048, 1)),
+], ids=lambda v: str(v))
+@pytest.mark.parametrize("force,comp", [((0, 0, 0), False), ((1e-5, -2e-5, 0), False),
+                                        ((1e-5, 0, 0), True)], ids=["plain", "force", "comp"])
+def test_large_narrow_storage_steps_equal_per_node_steps_and_oracle(storage, lattice, dims, force,
+                                                                    comp):
+    """Periodic boxes of 2^20 nodes and more in FP32, FP16, BF16 or e4m11
+    storage, in the shapes of the two-node FP64 test: their two-lattice
+    steps (one node per work-item, with row addressing at nx = 128 for FP32
+    and e4m11) against the AA pattern and an all-fluid mask, and the
+    oracle."""
+    assert dims[0] * dims[1] * dims[2] >= 1 << 20
+    print(f"large narrow {lattice} {dims} {storage} F={force} comp={comp}", flush=True)
+    _narrow_storage_kernels_agree(storage, lattice, dims, force, comp, (1, 1, 2))
+
+
 @pytest.mark.parametrize("storage", ["f32", "e4m11"])
 @pytest.mark.parametrize("lattice,dims", [
     (W.D2Q9, (64, 50, 1)), (W.D3Q19, (64, 24, 10)), (W.D3Q19, (256, 5, 3)), (W.D3Q27, (128, 9, 7)),

@@ -49,8 +49,9 @@ struct Impl {
             }
         }
         // Row addressing where it measured faster (D3Q19 256^3 and 512^3):
-        // e4m11 storage +23 % (its step is bound by the conversion
-        // arithmetic), FP32 +0.5 %; FP16 and BF16 ran 2-6 % slower with it.
+        // e4m11 storage +26 % (its step is bound by instruction issue, two
+        // thirds of it the conversions), FP32 +0.5-0.9 %; FP16 and BF16 ran
+        // 2-6 % slower with it.
         if constexpr (!K::walls && (std::is_same_v<S, e4m11> || std::is_same_v<S, float>)) {
             if (c->rows) {
                 hipLaunchKernelGGL((k_step_ab_rows<L, S, K::force, K::comp, kNtStores>), c->grid, c->block, 0,

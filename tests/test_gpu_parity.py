@@ -28,6 +28,9 @@ CASES_3D = [
     # lattice, dims, tau, bc, force, steps, input kind
     (W.D3Q19, (37, 29, 23), 0.6, (0, 0, 0), (0, 0, 0), 20, "tg"),
     (W.D3Q19, (300, 7, 5), 0.7, (0, 0, 0), (2e-6, -1e-6, 1e-6), 12, "tg"),
+    # rows of 2 and 3 workgroups placed on one XCD each (row-blocks a multiple of 8)
+    (W.D3Q19, (300, 8, 5), 0.7, (0, 1, 0), (1e-5, 0, 0), 12, "channel"),
+    (W.D3Q19, (530, 4, 6), 0.7, (0, 0, 0), (2e-6, -1e-6, 1e-6), 10, "tg"),
     (W.D3Q19, (40, 20, 18), 0.9, (0, 1, 0), (1e-5, 0, 0), 30, "channel"),
     (W.D3Q19, (33, 17, 12), 0.75, (2, 1, 2), (1e-5, 2e-6, -3e-6), 25, "channel"),
     (W.D3Q19, (1, 34, 1), 0.9, (0, 1, 0), (1e-5, 0, 0), 60, "channel"),
@@ -36,6 +39,7 @@ CASES_3D = [
     (W.D3Q19, (9, 11, 13), 0.55, (1, 1, 1), (1e-5, -1e-5, 1e-5), 15, "channel"),
     (W.D2Q9, (70, 33, 1), 0.8, (0, 1, 0), (1e-5, 0, 0), 40, "channel"),
     (W.D2Q9, (300, 45, 1), 1.2, (2, 0, 0), (0, 1e-5, 0), 30, "channel"),
+    (W.D2Q9, (600, 16, 1), 0.8, (2, 0, 0), (0, 1e-5, 0), 20, "channel"),
     (W.D2Q9, (64, 64, 1), 0.8, (0, 0, 0), (0, 0, 0), 50, "tg"),
     (W.D2Q9, (45, 37, 1), 0.7, (0, 0, 0), (1e-5, -2e-5, 0), 21, "tg"),
 ]
@@ -209,6 +213,7 @@ def _narrow_storage_kernels_agree(storage, lattice, dims, force, comp, counts):
 @pytest.mark.parametrize("lattice,dims", [
     (W.D3Q19, (2, 1024, 512)), (W.D3Q19, (34, 200, 155)), (W.D3Q19, (128, 96, 86)),
     (W.D3Q19, (1030, 33, 31)), (W.D2Q9, (18, 58255, 1)), (W.D2Q9, (514, 2048, 1)),
+    (W.D3Q19, (512, 64, 32)),
 ], ids=lambda v: str(v))
 @pytest.mark.parametrize("force,comp", [((0, 0, 0), False), ((1e-5, -2e-5, 0), False),
                                         ((1e-5, 0, 0), True)], ids=["plain", "force", "comp"])
@@ -227,6 +232,7 @@ def test_large_narrow_storage_steps_equal_per_node_steps_and_oracle(storage, lat
 @pytest.mark.parametrize("storage", ["f32", "e4m11"])
 @pytest.mark.parametrize("lattice,dims", [
     (W.D2Q9, (64, 50, 1)), (W.D3Q19, (64, 24, 10)), (W.D3Q19, (256, 5, 3)), (W.D3Q27, (128, 9, 7)),
+    (W.D3Q19, (512, 8, 3)), (W.D2Q9, (1024, 16, 1)),
 ], ids=lambda v: str(v))
 @pytest.mark.parametrize("force,comp", [((0, 0, 0), False), ((1e-5, -2e-5, 0), False),
                                         ((1e-5, 0, 0), True)], ids=["plain", "force", "comp"])
@@ -234,9 +240,11 @@ def test_row_addressed_steps_equal_per_node_steps_and_oracle(storage, lattice, d
     """Periodic boxes with nx a power of two (64 to the tile length) in FP32
     or e4m11 storage step one node per work-item with the addresses of the
     source rows computed once per wavefront (rows of one and of several
-    wavefronts, D2Q9, D3Q19, D3Q27).  The AA pattern and an all-fluid solid
-    mask take the per-node kernels, which apply the same collision to the
-    same populations: all three agree bit for bit after 1, 2, 3 and 6 steps.
+    wavefronts, rows of two and four workgroups; D2Q9, D3Q19, D3Q27).  The
+    AA pattern and an all-fluid solid mask take the per-node kernels (the
+    masked one with each row's workgroups on one XCD), which apply the same
+    collision to the same populations: all three agree bit for bit after 1,
+    2, 3 and 6 steps.
     From a state exactly representable in the storage format, the first step
     is the FP64 oracle's step rounded to the format, within one unit in the
     last place plus FP32 arithmetic error."""

@@ -86,9 +86,10 @@ struct lbm_ctx {
     // two, 64 <= nx <= tile length): the one-node AB step of a box without
     // walls may take k_step_ab_rows (FP32 and e4m11 storage).
     bool rows = false;
-    // Rows of more than one workgroup, row-blocks a multiple of 8: the
-    // one-node AB step (k_step_ab) places each row's workgroups on one XCD.
+    // Rows of more than one workgroup and ny a multiple of 8: the one-node AB
+    // steps run on grid_xcd, with each row's workgroups on one XCD.
     bool xcd_rows = false;
+    dim3 grid_xcd;
 
     // Rows per segment of the streamed D2Q9 launches (0: not planned yet).
     int stream_rows = 0;
@@ -156,22 +157,13 @@ inline IoArgs io_args(const lbm_ctx* c)
     return p;
 }
 
-// m = ceil(2^40 / d): floor(n m / 2^40) = floor(n / d) when n e < 2^40,
-// e = m d - 2^40 < d; so for every n < 2^24 and d < 2^16 (workgroup counts
-// below 2^23, grid extents up to 65535).
-inline unsigned long long div_magic(unsigned d)
-{
-    return ((1ull << 40) + d - 1) / d;
-}
-
 template <class C>
 inline StepArgs<C> step_args(const lbm_ctx* c)
 {
     StepArgs<C> p;
     p.g = dims_of(c);
     p.bx_shift = c->bx_shift;
-    p.xcd_mx = c->xcd_rows ? div_magic(c->grid.x) : 0;
-    p.xcd_my = c->xcd_rows ? div_magic(c->grid.y) : 0;
+    p.xcd_rows = 0;  // launches on grid_xcd set it
     p.c.omega = C(c->omega);
     for (int d = 0; d < 3; ++d) p.c.F[d] = C(c->F[d]);
     const double half = 1.0 - 0.5 * c->omega;

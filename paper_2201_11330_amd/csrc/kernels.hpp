@@ -206,36 +206,21 @@ __device__ __forceinline__ bool node_of_item(const Dims& g, int bx_shift, int& x
     return x < g.nx && y < g.ny;
 }
 
-// As node_of_item, for a launch whose rows span gridDim.x > 1 workgroups, with
-// the workgroups renumbered so that those of one row run on one XCD.  The
-// dispatcher hands workgroup k (in x-fastest order) to XCD k mod 8; the
-// renumbering gives the gridDim.x workgroups of row-block r the ids
-// k = 8 (q gridDim.x + xb) + (r mod 8), q = r / 8, xb = 0 .. gridDim.x - 1,
-// which go to one XCD one after another.  The lines at the seams between
-// them, which the x-shifted loads of both sides read, then come into one L2
-// instead of two.  A bijection when gridDim.y * gridDim.z is a multiple of 8.
-// Divisions by gridDim.x and gridDim.y multiply by m = ceil(2^40 / d) (see
-// div_magic): exact for numerators below 2^24 and divisors below 2^16.
-__device__ __forceinline__ unsigned div_by_magic(unsigned n, unsigned long long m)
+// As node_of_item, for rows of more than one workgroup (BX = 256 nodes per
+// workgroup, one row per workgroup), launched on the grid
+// (8 G, ny / 8, nz) with G workgroups per row.  The dispatcher hands
+// workgroup k (in x-fastest order) to XCD k mod 8, and k mod 8 = blockIdx.x
+// mod 8 here; blockIdx.x = 8 xb + j is part xb of row 8 blockIdx.y + j, so
+// the G workgroups of a row have consecutive ids among those of one XCD.
+// The lines at the seams between them, which the x-shifted loads of both
+// sides read, then come into one L2 instead of two.
+__device__ __forceinline__ bool node_of_item_rows_on_xcd(const Dims& g, int bx_shift, int& x, int& y, int& z)
 {
-    return unsigned((static_cast<unsigned long long>(n) * m) >> 40);
-}
-
-__device__ __forceinline__ bool node_of_item_rows_on_xcd(const Dims& g, int bx_shift, unsigned long long mx,
-                                                         unsigned long long my, int& x, int& y, int& z)
-{
-    const unsigned gx = gridDim.x, gy = gridDim.y;
-    const unsigned k = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    const unsigned s = k >> 3;
-    const unsigned q = div_by_magic(s, mx);
-    const unsigned r = q * 8 + (k & 7);
-    const unsigned zb = div_by_magic(r, my);
     const int tx = threadIdx.x & ((1 << bx_shift) - 1);
-    const int ty = threadIdx.x >> bx_shift;
-    x = int((s - q * gx) << bx_shift) + tx;
-    y = int(r - zb * gy) * (blockDim.x >> bx_shift) + ty;
-    z = int(zb);
-    return x < g.nx && y < g.ny;
+    x = int((blockIdx.x >> 3) << bx_shift) + tx;
+    y = int(blockIdx.y * 8 + (blockIdx.x & 7));
+    z = blockIdx.z;
+    return x < g.nx;
 }
 
 // In-plane index of x + sgn*e_a for every a, and whether that node is a wall.
@@ -447,19 +432,16 @@ template <class C>
 struct StepArgs {
     Dims g;
     int bx_shift;
-    // Nonzero: k_step_ab places each row's workgroups on one XCD
-    // (node_of_item_rows_on_xcd, with the reciprocals of the grid's x and y
-    // extents).  Measured on MI355X, D3Q19 512^3: FP16 and BF16 storage
-    // 72.6-72.8 -> 77.5 % of the HBM peak; the FP64 channel 512x128x128 +0.7 %.
-    unsigned long long xcd_mx, xcd_my;
+    // Nonzero: the launch is on the grid of node_of_item_rows_on_xcd, with
+    // each row's workgroups on one XCD (one-node AB steps only).
+    int xcd_rows;
     CollideArgs<C> c;
 };
 
 template <class C>
 __device__ __forceinline__ bool step_node(const StepArgs<C>& p, int& x, int& y, int& z)
 {
-    return p.xcd_mx ? node_of_item_rows_on_xcd(p.g, p.bx_shift, p.xcd_mx, p.xcd_my, x, y, z)
-                    : node_of_item(p.g, p.bx_shift, x, y, z);
+    return p.xcd_rows ? node_of_item_rows_on_xcd(p.g, p.bx_shift, x, y, z) : node_of_item(p.g, p.bx_shift, x, y, z);
 }
 
 // Two FP64 populations of neighbouring nodes (x0, x0 + 1), moved as one
@@ -578,9 +560,7 @@ __global__ LBM_STEP_BOUNDS void k_step_ab_rows(const S* __restrict__ src, S* __r
     constexpr int Q = Lattice<L>::Q;
     const Dims& g = p.g;
     int x, y, z;
-    // Plain workgroup order: placing a row's workgroups on one XCD measured
-    // 2.5-3 % slower for this kernel (FP32 and e4m11, 512^3).
-    if (!node_of_item(g, p.bx_shift, x, y, z)) return;  // whole wavefronts (rows of >= 64 nodes)
+    if (!step_node(p, x, y, z)) return;  // whole wavefronts (rows of >= 64 nodes)
     y = __builtin_amdgcn_readfirstlane(y);
     z = __builtin_amdgcn_readfirstlane(z);
     const int TS = g.S;

@@ -61,7 +61,8 @@ void plan_launch(lbm_ctx* c)
     c->bx_shift = shift;
     c->block = dim3(256, 1, 1);
     c->grid = dim3((c->nx + bx - 1) / bx, (c->ny + by - 1) / by, c->nz);
-    c->xcd_rows = c->grid.x > 1 && (unsigned long long)c->grid.y * c->grid.z % 8 == 0;
+    c->xcd_rows = c->grid.x > 1 && c->ny % 8 == 0;  // then bx = 256, one row per workgroup
+    if (c->xcd_rows) c->grid_xcd = dim3(c->grid.x * 8, unsigned(c->ny / 8), c->nz);
 
     // Two nodes per work-item: nx/2 work-items per row.  Only on boxes of at
     // least 2^20 nodes (a small box is bound by launch latency and runs

@@ -28,9 +28,9 @@ CASES_3D = [
     # lattice, dims, tau, bc, force, steps, input kind
     (W.D3Q19, (37, 29, 23), 0.6, (0, 0, 0), (0, 0, 0), 20, "tg"),
     (W.D3Q19, (300, 7, 5), 0.7, (0, 0, 0), (2e-6, -1e-6, 1e-6), 12, "tg"),
-    # rows of 2 and 3 workgroups placed on one XCD each (row-blocks a multiple of 8)
+    # rows of 2 and 3 workgroups placed on one XCD each (ny a multiple of 8)
     (W.D3Q19, (300, 8, 5), 0.7, (0, 1, 0), (1e-5, 0, 0), 12, "channel"),
-    (W.D3Q19, (530, 4, 6), 0.7, (0, 0, 0), (2e-6, -1e-6, 1e-6), 10, "tg"),
+    (W.D3Q19, (530, 8, 3), 0.7, (0, 0, 0), (2e-6, -1e-6, 1e-6), 10, "tg"),
     (W.D3Q19, (40, 20, 18), 0.9, (0, 1, 0), (1e-5, 0, 0), 30, "channel"),
     (W.D3Q19, (33, 17, 12), 0.75, (2, 1, 2), (1e-5, 2e-6, -3e-6), 25, "channel"),
     (W.D3Q19, (1, 34, 1), 0.9, (0, 1, 0), (1e-5, 0, 0), 60, "channel"),
@@ -240,11 +240,10 @@ def test_row_addressed_steps_equal_per_node_steps_and_oracle(storage, lattice, d
     """Periodic boxes with nx a power of two (64 to the tile length) in FP32
     or e4m11 storage step one node per work-item with the addresses of the
     source rows computed once per wavefront (rows of one and of several
-    wavefronts, rows of two and four workgroups; D2Q9, D3Q19, D3Q27).  The
-    AA pattern and an all-fluid solid mask take the per-node kernels (the
-    masked one with each row's workgroups on one XCD), which apply the same
-    collision to the same populations: all three agree bit for bit after 1,
-    2, 3 and 6 steps.
+    wavefronts, rows of two and four workgroups on one XCD each; D2Q9,
+    D3Q19, D3Q27).  The AA pattern and an all-fluid solid mask take the
+    per-node kernels, which apply the same collision to the same
+    populations: all three agree bit for bit after 1, 2, 3 and 6 steps.
     From a state exactly representable in the storage format, the first step
     is the FP64 oracle's step rounded to the format, within one unit in the
     last place plus FP32 arithmetic error."""

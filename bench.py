@@ -359,7 +359,22 @@ def run_paper_sphere(steps=100, warmup=5, storage="f64"):
             "mlups": round(nodes * steps / (ms * 1e-3) / 1e6, 1),
             "bytes_per_update": blu,
             "achieved_gbs": round(blu * nodes * steps / (ms * 1e-3) / 1e9, 1),
-            "sphere_force_x": drag[0]}
+            "sphere_force_x": drag[0],
+            "paper_context": PAPER_CONTEXT}
+
+
+# The paper's own figures for this box, as context (other hardware, not a
+# target).
+PAPER_CONTEXT = {
+    "hardware": "ThetaGPU node: 2x AMD Rome 64-core CPUs, 8x NVIDIA A100 (Sec. 5, node table)",
+    "workload": "flow past a sphere, D3Q27 512x128x128, FP64, inlet/outlet boundaries, 1-8 GPUs",
+    "mlups": None,
+    "note": "the paper gives its MLUPS in a figure only (Sec. 6), not in its text; its code "
+            "profile (Sec. 3: 8 ranks, one A100 each, 6401 steps, 0.11 s in total) samples "
+            "host time only. "
+            "For scale: an A100's ~1.555 TB/s allows ~3,600 MLUPS at 432 B per D3Q27 FP64 "
+            "update (NVIDIA's bandwidth figure, not the paper's)",
+}
 
 
 def run_small_2d(n=128, steps=1000, tau=0.8):

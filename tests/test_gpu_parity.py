@@ -31,6 +31,7 @@ CASES_3D = [
     # rows of 2 and 3 workgroups placed on one XCD each (ny a multiple of 8)
     (W.D3Q19, (300, 8, 5), 0.7, (0, 1, 0), (1e-5, 0, 0), 12, "channel"),
     (W.D3Q19, (530, 8, 3), 0.7, (0, 0, 0), (2e-6, -1e-6, 1e-6), 10, "tg"),
+    (W.D3Q19, (257, 16, 2), 0.8, (0, 0, 0), (1e-5, 0, 0), 8, "tg"),  # second workgroup 1/256 busy
     (W.D3Q19, (40, 20, 18), 0.9, (0, 1, 0), (1e-5, 0, 0), 30, "channel"),
     (W.D3Q19, (33, 17, 12), 0.75, (2, 1, 2), (1e-5, 2e-6, -3e-6), 25, "channel"),
     (W.D3Q19, (1, 34, 1), 0.9, (0, 1, 0), (1e-5, 0, 0), 60, "channel"),

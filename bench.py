@@ -528,6 +528,24 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
+def build_record():
+    """What the timed library was built from and runs on: the in-tree
+    library's file hash, the hash of its sources and compiler flags
+    (kernel_sources_sha256), the flags, and the device."""
+    import torch
+
+    from paper_2201_11330_amd import build as hip_build
+    from paper_2201_11330_amd import lbm
+
+    with open(lbm.LIB_PATH, "rb") as fh:
+        lib_sha = hashlib.sha256(fh.read()).hexdigest()
+    props = torch.cuda.get_device_properties(0)
+    return {"library": os.path.relpath(lbm.LIB_PATH, ROOT), "library_sha256": lib_sha,
+            "sources_sha256": kernel_sources_sha256(), "hipcc_flags": " ".join(hip_build.HIPCC_FLAGS),
+            "device": props.name, "arch": getattr(props, "gcnArchName", None),
+            "torch": torch.__version__, "hip": torch.version.hip}
+
+
 def measured_traffic(storage, pattern, n):
     """HBM bytes per launch of the timed kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE figures (scaled by a plain copy of known size),
@@ -713,6 +731,7 @@ def main():
     }
     if "copy_probe" in r:
         out["copy_probe"] = r["copy_probe"]
+    out["build"] = build_record()
     if not args.no_extras and args.storage == "f64":
         for name, fn in EXTRA_LINES.items():
             out[name] = fn(args, mlups)

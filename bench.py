@@ -674,7 +674,7 @@ EXTRA_LINES = {
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not built)"}))
         sys.exit(2)
     import torch

@@ -24,6 +24,11 @@ def test_timed_kernel_name():
     assert bench.step_kernel_name(256, "f16", "ab") == "k_step_ab<D3Q19,f16>"
     assert bench.step_kernel_name(255, "f64", "ab") == "k_step_ab<D3Q19,f64>"  # odd nx
     assert bench.step_kernel_name(64, "f64", "ab") == "k_step_ab<D3Q19,f64>"   # < 2^20 nodes
+    # FP32 and e4m11 two-lattice steps on rows of a power-of-two length
+    assert bench.step_kernel_name(512, "e4m11", "ab") == "k_step_ab_rows<D3Q19,e4m11>"
+    assert bench.step_kernel_name(128, "f32", "ab") == "k_step_ab_rows<D3Q19,f32>"
+    assert bench.step_kernel_name(96, "f32", "ab") == "k_step_ab<D3Q19,f32>"
+    assert bench.step_kernel_name(256, "e4m11", "aa") == "k_step_aa<D3Q19,e4m11>"
 
 
 def test_counter_figures_follow_the_kernel_sources():
